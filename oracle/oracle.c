@@ -1,0 +1,260 @@
+/*
+ * CPU oracle for the swept time-space decomposition hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg do.  It shares no source, header, table or helper with the
+ * HIP path.
+ *
+ * What it computes is the plain, slow, obviously correct definition: one full
+ * explicit timestep over the whole periodic grid per loop iteration, exactly
+ * the "classic" decomposition of Magee & Niemeyer (arXiv 1612.02495, Sec. 4.4).
+ * The swept rule reorders *where and when* these same updates are evaluated
+ * and does not change the numerical scheme (Sec. 2), so the plain timestepper
+ * is the reference the swept result must reproduce.
+ *
+ * Precision and operation order (IEEE-754, round to nearest even, no
+ * contraction into FMA: build with -ffp-contract=off, no -ffast-math):
+ *
+ *   Heat (Sec. 4.1, Eq. HeatDisc; Appendix, final FTCS form):
+ *       Fo = (alpha*dt)/(dx*dx), c = 1 - 2*Fo   (computed once, in double)
+ *       T_i^{m+1} = Fo*(T_{i+1}^m + T_{i-1}^m) + c*T_i^m
+ *
+ *   Kuramoto-Sivashinsky (Sec. 4.1, Eq. KSDisc; Appendix, RK2 midpoint):
+ *       with a=u_{i+1}, b=u_{i-1}, aa=u_{i+2}, bb=u_{i-2}, o=u_i,
+ *       nl = (a*a - b*b) * (1/(4dx))                 (u u_x = (u^2/2)_x)
+ *       d2 = ((a + b) - 2*o) * (1/dx^2)              (u_xx)
+ *       d4 = ((((aa - 4*a) + 6*o) - 4*b) + bb) * (1/dx^4)   (u_xxxx)
+ *       f  = -((nl + d2) + d4)
+ *       predictor  u^{m+1/2}_i = u^m_i + (dt/2) * f(u^m)_i       for all i, then
+ *       final      u^{m+1}_i   = u^m_i + dt * f(u^{m+1/2})_i
+ *     The inverses 1/(4dx), 1/dx^2 and 1/dx^4 = (1/dx^2)^2 are formed once and
+ *     multiplied in, as Sec. 5 (division avoidance) describes.  The printed
+ *     "+2u_i" in the u_xx numerator is read as "-2u_i" (the central second
+ *     difference; with "+" the term is not a derivative and sum(u) would not be
+ *     conserved).
+ *
+ *   Periodic boundaries: neighbour i+k is (i+k) mod n (Sec. 4.1; Appendix).
+ *
+ * The float entry points run the same order in single precision, with the
+ * constants formed in double and rounded once to float.
+ *
+ * Heat adjoint (not in the paper; the derivation is plain calculus on the
+ * discrete scheme above): for J = 1/2 ||u_T - y||^2 with u_{m+1} = A(alpha) u_m,
+ *   lambda_T = u_T - y,  lambda_m = A^T lambda_{m+1}  (A is symmetric here),
+ *   dJ/du_0 = lambda_0,
+ *   dJ/dalpha = (dt/dx^2) * sum_{m<T} sum_i lambda_{m+1,i} (u_{m,i-1} + u_{m,i+1} - 2 u_{m,i}).
+ * Forward states are recomputed from checkpoints every K steps.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL -1
+#define ORACLE_ENOMEM -3
+
+static int64_t wrap(int64_t i, int64_t n) {
+    int64_t r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+/* ---------------------------------------------------------------- heat -- */
+
+static void heat_step_f64(const double* u, double* v, int64_t n, double fo, double c) {
+    for (int64_t i = 0; i < n; ++i) {
+        double left = u[wrap(i - 1, n)];
+        double right = u[wrap(i + 1, n)];
+        v[i] = fo * (right + left) + c * u[i];
+    }
+}
+
+static void heat_step_f32(const float* u, float* v, int64_t n, float fo, float c) {
+    for (int64_t i = 0; i < n; ++i) {
+        float left = u[wrap(i - 1, n)];
+        float right = u[wrap(i + 1, n)];
+        v[i] = fo * (right + left) + c * u[i];
+    }
+}
+
+int oracle_heat_f64(double* u, int64_t n, double alpha, double dt, double dx, int64_t steps) {
+    if (!u || n < 1 || steps < 0) return ORACLE_EINVAL;
+    double fo = (alpha * dt) / (dx * dx);
+    double c = 1.0 - 2.0 * fo;
+    double* v = (double*)malloc((size_t)n * sizeof(double));
+    if (!v) return ORACLE_ENOMEM;
+    double* cur = u;
+    double* nxt = v;
+    for (int64_t m = 0; m < steps; ++m) {
+        heat_step_f64(cur, nxt, n, fo, c);
+        double* t = cur; cur = nxt; nxt = t;
+    }
+    if (cur != u) memcpy(u, cur, (size_t)n * sizeof(double));
+    free(v);
+    return ORACLE_OK;
+}
+
+int oracle_heat_f32(float* u, int64_t n, double alpha, double dt, double dx, int64_t steps) {
+    if (!u || n < 1 || steps < 0) return ORACLE_EINVAL;
+    double fo_d = (alpha * dt) / (dx * dx);
+    float fo = (float)fo_d;
+    float c = (float)(1.0 - 2.0 * fo_d);
+    float* v = (float*)malloc((size_t)n * sizeof(float));
+    if (!v) return ORACLE_ENOMEM;
+    float* cur = u;
+    float* nxt = v;
+    for (int64_t m = 0; m < steps; ++m) {
+        heat_step_f32(cur, nxt, n, fo, c);
+        float* t = cur; cur = nxt; nxt = t;
+    }
+    if (cur != u) memcpy(u, cur, (size_t)n * sizeof(float));
+    free(v);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------ KS -- */
+
+typedef struct { double i4dx, idx2, idx4, dt, dth; } ks_consts;
+
+static ks_consts ks_make(double dt, double dx) {
+    ks_consts k;
+    k.i4dx = 1.0 / (4.0 * dx);
+    k.idx2 = 1.0 / (dx * dx);
+    k.idx4 = k.idx2 * k.idx2;
+    k.dt = dt;
+    k.dth = 0.5 * dt;
+    return k;
+}
+
+static double ks_rhs_f64(const double* v, int64_t n, int64_t i, const ks_consts* k) {
+    double bb = v[wrap(i - 2, n)];
+    double b = v[wrap(i - 1, n)];
+    double o = v[i];
+    double a = v[wrap(i + 1, n)];
+    double aa = v[wrap(i + 2, n)];
+    double nl = (a * a - b * b) * k->i4dx;
+    double d2 = ((a + b) - 2.0 * o) * k->idx2;
+    double d4 = ((((aa - 4.0 * a) + 6.0 * o) - 4.0 * b) + bb) * k->idx4;
+    return -((nl + d2) + d4);
+}
+
+static float ks_rhs_f32(const float* v, int64_t n, int64_t i, float i4dx, float idx2, float idx4) {
+    float bb = v[wrap(i - 2, n)];
+    float b = v[wrap(i - 1, n)];
+    float o = v[i];
+    float a = v[wrap(i + 1, n)];
+    float aa = v[wrap(i + 2, n)];
+    float nl = (a * a - b * b) * i4dx;
+    float d2 = ((a + b) - 2.0f * o) * idx2;
+    float d4 = ((((aa - 4.0f * a) + 6.0f * o) - 4.0f * b) + bb) * idx4;
+    return -((nl + d2) + d4);
+}
+
+int oracle_ks_f64(double* u, int64_t n, double dt, double dx, int64_t steps) {
+    if (!u || n < 1 || steps < 0) return ORACLE_EINVAL;
+    ks_consts k = ks_make(dt, dx);
+    double* up = (double*)malloc((size_t)n * sizeof(double));
+    if (!up) return ORACLE_ENOMEM;
+    for (int64_t m = 0; m < steps; ++m) {
+        for (int64_t i = 0; i < n; ++i) up[i] = u[i] + k.dth * ks_rhs_f64(u, n, i, &k);
+        for (int64_t i = 0; i < n; ++i) u[i] = u[i] + k.dt * ks_rhs_f64(up, n, i, &k);
+    }
+    free(up);
+    return ORACLE_OK;
+}
+
+int oracle_ks_f32(float* u, int64_t n, double dt, double dx, int64_t steps) {
+    if (!u || n < 1 || steps < 0) return ORACLE_EINVAL;
+    ks_consts k = ks_make(dt, dx);
+    float i4dx = (float)k.i4dx, idx2 = (float)k.idx2, idx4 = (float)k.idx4;
+    float fdt = (float)k.dt, fdth = (float)k.dth;
+    float* up = (float*)malloc((size_t)n * sizeof(float));
+    if (!up) return ORACLE_ENOMEM;
+    for (int64_t m = 0; m < steps; ++m) {
+        for (int64_t i = 0; i < n; ++i) up[i] = u[i] + fdth * ks_rhs_f32(u, n, i, i4dx, idx2, idx4);
+        for (int64_t i = 0; i < n; ++i) u[i] = u[i] + fdt * ks_rhs_f32(up, n, i, i4dx, idx2, idx4);
+    }
+    free(up);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------- heat adjoint -- */
+
+/* Neumaier-compensated accumulator: keeps the reference sums of the
+ * objective and of dJ/dalpha accurate to a few ulps regardless of length. */
+typedef struct { double s, c; } acc_t;
+static void acc_add(acc_t* a, double x) {
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+static double acc_get(const acc_t* a) { return a->s + a->c; }
+
+/*
+ * u0, y: n values each.  Outputs: g_u0 (n values), *g_alpha, *J.
+ * Checkpoints every `ckpt` steps (0 = choose ~sqrt(steps)).
+ */
+int oracle_heat_adjoint_f64(const double* u0, const double* y, int64_t n, double alpha, double dt,
+                            double dx, int64_t steps, int64_t ckpt, double* g_u0, double* g_alpha,
+                            double* J) {
+    if (!u0 || !y || !g_u0 || !g_alpha || !J || n < 1 || steps < 0) return ORACLE_EINVAL;
+    double fo = (alpha * dt) / (dx * dx);
+    double c = 1.0 - 2.0 * fo;
+    double dfo = dt / (dx * dx); /* d Fo / d alpha */
+    int64_t K = ckpt;
+    if (K <= 0) {
+        K = (int64_t)ceil(sqrt((double)(steps > 0 ? steps : 1)));
+        if (K < 1) K = 1;
+    }
+    int64_t nseg = steps > 0 ? (steps + K - 1) / K : 0;
+    size_t nb = (size_t)n * sizeof(double);
+    double* ck = (double*)malloc(nb * (size_t)(nseg > 0 ? nseg : 1));
+    double* seg = (double*)malloc(nb * (size_t)(K + 1));
+    double* lam = (double*)malloc(nb);
+    double* tmp = (double*)malloc(nb);
+    if (!ck || !seg || !lam || !tmp) {
+        free(ck); free(seg); free(lam); free(tmp);
+        return ORACLE_ENOMEM;
+    }
+    /* forward: store the state at the start of every segment */
+    memcpy(tmp, u0, nb);
+    for (int64_t s = 0; s < nseg; ++s) {
+        memcpy(ck + (size_t)s * n, tmp, nb);
+        int64_t len = (s == nseg - 1) ? steps - s * K : K;
+        for (int64_t m = 0; m < len; ++m) {
+            heat_step_f64(tmp, lam, n, fo, c);
+            memcpy(tmp, lam, nb);
+        }
+    }
+    /* tmp = u_T */
+    acc_t jacc = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) {
+        double d = tmp[i] - y[i];
+        lam[i] = d;
+        acc_add(&jacc, 0.5 * d * d);
+    }
+    acc_t gacc = {0.0, 0.0};
+    for (int64_t s = nseg - 1; s >= 0; --s) {
+        int64_t len = (s == nseg - 1) ? steps - s * K : K;
+        memcpy(seg, ck + (size_t)s * n, nb);
+        for (int64_t m = 0; m < len; ++m) heat_step_f64(seg + (size_t)m * n, seg + (size_t)(m + 1) * n, n, fo, c);
+        for (int64_t m = len - 1; m >= 0; --m) {
+            const double* um = seg + (size_t)m * n;
+            /* dJ/dalpha contribution of step m: <lambda_{m+1}, dA/dalpha u_m> */
+            for (int64_t i = 0; i < n; ++i) {
+                double lap = (um[wrap(i - 1, n)] + um[wrap(i + 1, n)]) - 2.0 * um[i];
+                acc_add(&gacc, lam[i] * lap);
+            }
+            /* lambda_m = A^T lambda_{m+1}; A is symmetric for the periodic stencil */
+            heat_step_f64(lam, tmp, n, fo, c);
+            memcpy(lam, tmp, nb);
+        }
+    }
+    memcpy(g_u0, lam, nb);
+    *g_alpha = dfo * acc_get(&gacc);
+    *J = acc_get(&jacc);
+    free(ck); free(seg); free(lam); free(tmp);
+    return ORACLE_OK;
+}
