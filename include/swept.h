@@ -1,0 +1,158 @@
+/*
+ * swept.h -- C ABI of the MI355X (gfx950) swept time-space decomposition
+ * library for explicit 1-D periodic stencils.
+ *
+ * Method: Magee & Niemeyer, "An initial investigation of the performance of
+ * GPU-based swept time-space decomposition" (arXiv 1612.02495).  A workgroup
+ * advances one spatial tile ("node", Sec. 4.2) through many tiers of the
+ * space-time plane without leaving on-chip memory: an up-triangle phase, then
+ * diamond phases whose tiling is shifted by half a tile each time
+ * (the zig-zag of Sec. 4.2), then a closing down-triangle phase that emits the
+ * full solution row.  Only the two outermost stencil-radius bands of every
+ * tier ("edges", Sec. 4.2 Figs. firstorder/collection; four values per side
+ * per sub-step for the five-point stencil, Sec. 4.3) pass through HBM between
+ * launches.  The swept rule does not change the numerical scheme (Sec. 2), so
+ * every entry point below returns exactly what the plain timestepper returns
+ * for the same precision and operation order.
+ *
+ * Schemes (Sec. 4.1 and Appendix; periodic boundaries, index (i+k) mod n):
+ *   SWEPT_HEAT_FTCS  T_i^{m+1} = Fo (T_{i+1}^m + T_{i-1}^m) + (1 - 2 Fo) T_i^m,
+ *                    Fo = alpha dt / dx^2                       (Eq. HeatDisc)
+ *   SWEPT_KS_RK2     Kuramoto-Sivashinsky, 5-point central differences
+ *                    (Eq. KSDisc) advanced by the RK2 midpoint rule
+ *                    (predictor with dt/2, then final with dt).
+ *
+ * Conventions shared by all entry points
+ *   - Return value: SWEPT_OK (0) or a negative swept status code.  Nothing
+ *     crosses the ABI as an exception.  The message of the last failure on
+ *     the calling thread is available from swept_last_error().
+ *   - Argument validation happens before any HIP call: an invalid call
+ *     touches neither the device nor the caller's buffers.
+ *   - Device pointers are HIP device allocations owned by the caller,
+ *     contiguous, of the plan's dtype, aligned to the element size.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Runs are enqueued asynchronously on it; the caller synchronises.
+ *   - A plan owns its device workspace (edge strips and the naive ping-pong
+ *     buffer), allocated by swept_plan_create and freed by swept_plan_destroy.
+ *     A plan must not be used on two streams at the same time.
+ *   - The current HIP device at swept_plan_create is the plan's device; later
+ *     calls make it current for their duration.
+ */
+#ifndef SWEPT_H
+#define SWEPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SWEPT_OK 0
+#define SWEPT_EINVAL -1        /* bad argument                               */
+#define SWEPT_EUNSUPPORTED -2  /* valid request this build cannot tile       */
+#define SWEPT_ENOMEM -3        /* device allocation failed                   */
+#define SWEPT_EDEVICE -4       /* HIP runtime error (message in last_error)  */
+
+/* stencil kinds */
+#define SWEPT_HEAT_FTCS 0
+#define SWEPT_KS_RK2 1
+
+/* element types */
+#define SWEPT_F32 0
+#define SWEPT_F64 1
+
+/* phase engines (swept_plan_set_engine) */
+#define SWEPT_ENGINE_AUTO 0 /* wave-resident engine where it applies, else LDS */
+#define SWEPT_ENGINE_LDS 1  /* tile in LDS, two tier rows, one thread block    */
+#define SWEPT_ENGINE_WAVE 2 /* tile in the registers of one wave64, DPP halos   */
+
+typedef struct swept_plan_s* swept_plan;
+
+/*
+ * swept_plan_create -- build a plan for one periodic grid of n points.
+ *   out             receives the plan handle (host pointer, required).
+ *   n               number of grid points, >= tile width, multiple of it.
+ *   kind, dtype     SWEPT_HEAT_FTCS / SWEPT_KS_RK2, SWEPT_F32 / SWEPT_F64.
+ *   dt, dx          timestep and grid spacing (finite, dx != 0).
+ *   alpha           diffusivity (heat only; ignored for KS).
+ *   tile_width      points per tile ("node", Sec. 4.2): a multiple of 2s
+ *                   (s = 1 heat, 2 KS) and of 8 for KS, 4..4096; 0 picks one.
+ *   steps_per_cycle timesteps per full phase: 1..w/2 (heat), 1..w/8 (KS);
+ *                   0 = the pure triangle height (w/2 heat, w/8 KS).
+ * Discretisation constants are formed once on the host in double and, for
+ * SWEPT_F32, rounded once to float: Fo = (alpha*dt)/(dx*dx), 1-2Fo,
+ * 1/(4dx), 1/dx^2, (1/dx^2)^2, dt, dt/2 (inverses instead of divisions,
+ * Sec. 5).  Errors: EINVAL (bad argument), EUNSUPPORTED (n not tileable with
+ * a supported width), ENOMEM / EDEVICE (allocation).
+ */
+int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt, double dx,
+                      double alpha, int tile_width, int steps_per_cycle);
+
+/*
+ * swept_run -- advance u (device, n elements, in/out) by `steps` timesteps
+ * with the swept decomposition (Sec. 4.2-4.3): one up-triangle launch,
+ * diamond launches, one down-triangle launch; the last phase is a flattened
+ * (trapezoid) phase when steps is not a multiple of steps_per_cycle.
+ * steps == 0 is a no-op.  Result is bit-identical to naive_run.
+ */
+int swept_run(swept_plan p, void* u, int64_t steps, void* stream);
+
+/*
+ * naive_run -- the classic decomposition (Sec. 4.4): one kernel launch per
+ * sub-timestep reading and writing global memory, ping-ponging with the
+ * plan's buffer.  Same arguments and result as swept_run.
+ */
+int naive_run(swept_plan p, void* u, int64_t steps, void* stream);
+
+/*
+ * swept_plan_info -- report the plan's tile width, timesteps per full phase
+ * and device workspace size in bytes.  Any output pointer may be NULL.
+ */
+int swept_plan_info(swept_plan p, int* tile_width, int* steps_per_cycle, size_t* workspace_bytes);
+
+/*
+ * swept_plan_set_engine -- choose the kernel that runs the phases:
+ * SWEPT_ENGINE_AUTO, _LDS or _WAVE.  _WAVE requires tile_width = 64*P with
+ * P in {2, 4, 8, 16, 32} for heat and {4, 8, 16} for KS; otherwise the call
+ * fails with EUNSUPPORTED and the plan keeps its engine.
+ */
+int swept_plan_set_engine(swept_plan p, int engine);
+
+/* swept_plan_destroy -- free the plan and its workspace (NULL is a no-op). */
+void swept_plan_destroy(swept_plan p);
+
+/* swept_last_error -- message of the last failure on this thread ("" if none). */
+const char* swept_last_error(void);
+
+/*
+ * swept_schedule -- host-only query of the phase schedule swept_run uses.
+ * Writes the heights (in tiers: timesteps for heat, sub-steps for KS) of the
+ * edge sets passed between consecutive launches into heights[0..cap) and
+ * their number into *count; swept_run makes (*count + 1) launches.  Every
+ * height equals the full phase height except possibly the last.
+ * tile_width and steps_per_cycle as for swept_plan_create (0 = default for
+ * steps_per_cycle; tile_width must be given).  No device is touched.
+ */
+int swept_schedule(int kind, int tile_width, int steps_per_cycle, int64_t steps, int32_t* heights,
+                   int64_t cap, int64_t* count);
+
+/*
+ * swept_tile_geometry -- host-only query of the per-tile sizes the kernels
+ * use for a kind and tile width w (any output pointer may be NULL):
+ *   full_tiers       tiers of a full triangle: w/2 (heat), w/4 (KS), i.e. the
+ *                    triangle of Sec. 4.2 whose tier k holds w - 2 s k values;
+ *   row_values       values per LDS tier row, w + 2s (the two-row matrix of
+ *                    Sec. 4.2 holds 2 (w + 2) values for the 3-point stencil);
+ *   edge_slot_values values per edge slot in HBM, (w/2 + s) positions x 2.
+ * Errors: EINVAL for an unknown kind or an invalid width.  No device is touched.
+ */
+int swept_tile_geometry(int kind, int tile_width, int* full_tiers, int* row_values,
+                        int* edge_slot_values);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWEPT_H */

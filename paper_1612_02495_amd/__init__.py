@@ -1,0 +1,13 @@
+"""Swept time-space decomposition for explicit 1-D periodic stencils on MI355X.
+
+The computation lives in libswept.so (HIP kernels for gfx950 behind the C ABI
+of include/swept.h); this package is its Python binding.  Importing it does
+not load the library; the first call does.
+"""
+from .swept import (Plan, SweptError, naive_run, swept_last_error, swept_plan_create,
+                    swept_plan_destroy, swept_plan_info, swept_plan_set_engine, swept_run,
+                    swept_schedule, swept_tile_geometry)
+
+__all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
+           "swept_plan_set_engine", "swept_plan_destroy", "swept_last_error", "swept_schedule",
+           "swept_tile_geometry"]

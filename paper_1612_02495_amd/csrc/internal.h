@@ -1,0 +1,48 @@
+// Internal (non-ABI) declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "stencil.h"
+
+namespace swept {
+
+// One swept phase over the whole ring (Sec. 4.2): every tile first fills the
+// V between the incoming edge bands (hv tiers; hv == 0 means "read the full
+// row from u"), then climbs the triangle/trapezoid Lambda (hl tiers; hl == 0
+// means "write the full row to u").  Tiles of phase p start at
+// parity * w/2 + j*w; the edge bands live in 2*nt slots of (w + 2s) values.
+struct PhaseArgs {
+  void* u;       // device grid, n values
+  void* slots;   // device edge slots: slot A[j] at j, slot B[j] at nt + j
+  int64_t n;
+  int w;         // tile width
+  int64_t nt;    // tiles = n / w
+  int parity;    // 0: tiles start at j*w; 1: at j*w + w/2
+  int hv;        // V height in tiers (0 = load full row)
+  int hl;        // Lambda height in tiers (0 = store full row)
+};
+
+// Values per edge slot: (w/2 + s) positions, two tier parities each.
+__host__ __device__ inline int slot_values(int w, int s) { return w + 2 * s; }
+
+template <typename T>
+hipError_t launch_naive_heat(const T* in, T* out, int64_t n, const Consts<T>& k, hipStream_t st);
+template <typename T>
+hipError_t launch_naive_ks_predictor(const T* u, T* q, int64_t n, const Consts<T>& k, hipStream_t st);
+template <typename T>
+hipError_t launch_naive_ks_final(T* u, const T* q, int64_t n, const Consts<T>& k, hipStream_t st);
+
+template <int KIND, typename T>
+hipError_t launch_phase_lds(const PhaseArgs& a, const Consts<T>& k, hipStream_t st);
+template <int KIND, typename T>
+size_t phase_lds_bytes(int w);
+
+template <int KIND, typename T>
+hipError_t launch_phase_wave(const PhaseArgs& a, const Consts<T>& k, hipStream_t st);
+// Whether the wave-resident engine has a kernel for this kind and width.
+bool wave_engine_supports(int kind, int w);
+
+}  // namespace swept

@@ -1,0 +1,366 @@
+// C ABI of the swept library: argument validation, tiling, phase schedule,
+// workspace ownership and launch sequencing (declared in include/swept.h).
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "swept.h"
+
+using swept::Consts;
+using swept::PhaseArgs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(SWEPT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int radius_of(int kind) { return kind == SWEPT_KS_RK2 ? 2 : 1; }
+
+constexpr int kMinTile = 4;
+constexpr int kMaxTile = 4096;
+
+// Tile width rules: w = 2s * (tiers of a full triangle); KS phases must end
+// on whole timesteps (predictor + final), so w/4 has to be even.
+bool tile_ok(int kind, int w, std::string* why) {
+  const int s = radius_of(kind);
+  if (w < kMinTile || w > kMaxTile) {
+    *why = "tile_width must lie in [4, 4096]";
+    return false;
+  }
+  if (w % (2 * s) != 0) {
+    *why = "tile_width must be a multiple of 2 * stencil radius";
+    return false;
+  }
+  if (kind == SWEPT_KS_RK2 && w % 8 != 0) {
+    *why = "KS tile_width must be a multiple of 8 (whole timesteps per phase)";
+    return false;
+  }
+  return true;
+}
+
+// Tiers of a full (pure) triangle for this kind and width.
+int full_tiers(int kind, int w) {
+  const int s = radius_of(kind);
+  int h = w / (2 * s);
+  if (kind == SWEPT_KS_RK2) h &= ~1;
+  return h;
+}
+
+int tiers_per_step(int kind) { return kind == SWEPT_KS_RK2 ? 2 : 1; }
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+// Edge-set heights: full phases of h tiers, remainder last.
+void make_schedule(int h, int64_t tiers, std::vector<int32_t>* e) {
+  e->clear();
+  if (tiers <= 0) return;
+  const int64_t full = tiers / h;
+  const int64_t rem = tiers % h;
+  e->reserve((size_t)(full + (rem ? 1 : 0)));
+  for (int64_t i = 0; i < full; ++i) e->push_back(h);
+  if (rem) e->push_back((int32_t)rem);
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    err = hipGetDevice(&prev);
+    if (err != hipSuccess) { ok = false; return; }
+    if (prev != dev) {
+      err = hipSetDevice(dev);
+      ok = err == hipSuccess;
+    }
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (ok && hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct swept_plan_s {
+  int64_t n = 0;
+  int kind = 0;
+  int dtype = 0;
+  int s = 1;
+  int w = 0;
+  int h = 0;       // tiers per full phase
+  int64_t nt = 0;  // tiles
+  int engine = SWEPT_ENGINE_AUTO;
+  int device = 0;
+  void* slots = nullptr;
+  size_t slots_bytes = 0;
+  void* buf = nullptr;  // naive ping-pong / predictor buffer
+  size_t buf_bytes = 0;
+  Consts<double> kd{};
+  Consts<float> kf{};
+};
+
+namespace {
+
+size_t elem_size(int dtype) { return dtype == SWEPT_F64 ? sizeof(double) : sizeof(float); }
+
+bool use_wave(const swept_plan_s* p) {
+  if (p->engine == SWEPT_ENGINE_LDS) return false;
+  return swept::wave_engine_supports(p->kind, p->w);
+}
+
+template <int KIND, typename T>
+hipError_t launch_phase(const swept_plan_s* p, const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
+  if (use_wave(p)) return swept::launch_phase_wave<KIND, T>(a, k, st);
+  return swept::launch_phase_lds<KIND, T>(a, k, st);
+}
+
+template <typename T>
+hipError_t dispatch_phase(const swept_plan_s* p, const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
+  if (p->kind == SWEPT_HEAT_FTCS) return launch_phase<swept::kHeat, T>(p, a, k, st);
+  return launch_phase<swept::kKS, T>(p, a, k, st);
+}
+
+template <typename T>
+hipError_t run_naive(const swept_plan_s* p, T* u, int64_t steps, const Consts<T>& k, hipStream_t st) {
+  T* buf = static_cast<T*>(p->buf);
+  hipError_t e = hipSuccess;
+  if (p->kind == SWEPT_HEAT_FTCS) {
+    T* cur = u;
+    T* nxt = buf;
+    for (int64_t m = 0; m < steps; ++m) {
+      e = swept::launch_naive_heat<T>(cur, nxt, p->n, k, st);
+      if (e != hipSuccess) return e;
+      T* t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+    if (cur != u) e = hipMemcpyAsync(u, cur, (size_t)p->n * sizeof(T), hipMemcpyDeviceToDevice, st);
+    return e;
+  }
+  for (int64_t m = 0; m < steps; ++m) {
+    e = swept::launch_naive_ks_predictor<T>(u, buf, p->n, k, st);
+    if (e != hipSuccess) return e;
+    e = swept::launch_naive_ks_final<T>(u, buf, p->n, k, st);
+    if (e != hipSuccess) return e;
+  }
+  return e;
+}
+
+int choose_tile(int kind, int64_t n) {
+  // Largest power of two up to 1024 that divides n (the automatic tuner of
+  // the benchmark refines this per workload).
+  std::string why;
+  for (int w = 1024; w >= kMinTile; w >>= 1) {
+    if (n % w == 0 && n >= w && tile_ok(kind, w, &why)) return w;
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* swept_last_error(void) { return g_last_error.c_str(); }
+
+int swept_schedule(int kind, int tile_width, int steps_per_cycle, int64_t steps, int32_t* heights,
+                   int64_t cap, int64_t* count) {
+  if (kind != SWEPT_HEAT_FTCS && kind != SWEPT_KS_RK2) return fail(SWEPT_EINVAL, "unknown stencil kind");
+  std::string why;
+  if (!tile_ok(kind, tile_width, &why)) return fail(SWEPT_EINVAL, why);
+  const int hfull = full_tiers(kind, tile_width);
+  const int tps = tiers_per_step(kind);
+  if (steps_per_cycle < 0 || steps_per_cycle * tps > hfull)
+    return fail(SWEPT_EINVAL, "steps_per_cycle exceeds the triangle height of this tile width");
+  if (steps < 0) return fail(SWEPT_EINVAL, "steps must be >= 0");
+  if (!count) return fail(SWEPT_EINVAL, "count must not be NULL");
+  if (cap < 0 || (cap > 0 && !heights)) return fail(SWEPT_EINVAL, "heights must hold cap entries");
+  const int h = steps_per_cycle ? steps_per_cycle * tps : hfull;
+  std::vector<int32_t> e;
+  make_schedule(h, steps * tps, &e);
+  for (int64_t i = 0; i < cap && i < (int64_t)e.size(); ++i) heights[i] = e[(size_t)i];
+  *count = (int64_t)e.size();
+  return SWEPT_OK;
+}
+
+int swept_tile_geometry(int kind, int tile_width, int* full_tiers_out, int* row_values,
+                        int* edge_slot_values) {
+  if (kind != SWEPT_HEAT_FTCS && kind != SWEPT_KS_RK2) return fail(SWEPT_EINVAL, "unknown stencil kind");
+  std::string why;
+  if (!tile_ok(kind, tile_width, &why)) return fail(SWEPT_EINVAL, why);
+  const int s = radius_of(kind);
+  if (full_tiers_out) *full_tiers_out = full_tiers(kind, tile_width);
+  if (row_values) *row_values = tile_width + 2 * s;
+  if (edge_slot_values) *edge_slot_values = swept::slot_values(tile_width, s);
+  return SWEPT_OK;
+}
+
+int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt, double dx, double alpha,
+                      int tile_width, int steps_per_cycle) {
+  if (!out) return fail(SWEPT_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (kind != SWEPT_HEAT_FTCS && kind != SWEPT_KS_RK2) return fail(SWEPT_EINVAL, "unknown stencil kind");
+  if (dtype != SWEPT_F32 && dtype != SWEPT_F64) return fail(SWEPT_EINVAL, "unknown dtype");
+  if (n < kMinTile) return fail(SWEPT_EINVAL, "n must be >= 4");
+  if (!is_finite(dt) || !is_finite(dx) || dx == 0.0) return fail(SWEPT_EINVAL, "dt and dx must be finite, dx != 0");
+  if (kind == SWEPT_HEAT_FTCS && !is_finite(alpha)) return fail(SWEPT_EINVAL, "alpha must be finite");
+  if (tile_width < 0) return fail(SWEPT_EINVAL, "tile_width must be >= 0");
+  int w = tile_width;
+  std::string why;
+  if (w == 0) {
+    w = choose_tile(kind, n);
+    if (w == 0) return fail(SWEPT_EUNSUPPORTED, "no supported tile width divides n");
+  } else if (!tile_ok(kind, w, &why)) {
+    return fail(SWEPT_EINVAL, why);
+  }
+  if (n % w != 0 || n < w) return fail(SWEPT_EUNSUPPORTED, "n must be a positive multiple of tile_width");
+  const int hfull = full_tiers(kind, w);
+  const int tps = tiers_per_step(kind);
+  if (steps_per_cycle < 0 || steps_per_cycle * tps > hfull)
+    return fail(SWEPT_EINVAL, "steps_per_cycle exceeds the triangle height of this tile width");
+
+  auto* p = new (std::nothrow) swept_plan_s();
+  if (!p) return fail(SWEPT_ENOMEM, "host allocation failed");
+  p->n = n;
+  p->kind = kind;
+  p->dtype = dtype;
+  p->s = radius_of(kind);
+  p->w = w;
+  p->h = steps_per_cycle ? steps_per_cycle * tps : hfull;
+  p->nt = n / w;
+  // Discretisation constants in double, rounded once for float (Sec. 4.1, Sec. 5).
+  const double fo = (alpha * dt) / (dx * dx);
+  p->kd.fo = fo;
+  p->kd.c = 1.0 - 2.0 * fo;
+  p->kd.i4dx = 1.0 / (4.0 * dx);
+  p->kd.idx2 = 1.0 / (dx * dx);
+  p->kd.idx4 = p->kd.idx2 * p->kd.idx2;
+  p->kd.dt = dt;
+  p->kd.dth = 0.5 * dt;
+  p->kf.fo = (float)p->kd.fo;
+  p->kf.c = (float)p->kd.c;
+  p->kf.i4dx = (float)p->kd.i4dx;
+  p->kf.idx2 = (float)p->kd.idx2;
+  p->kf.idx4 = (float)p->kd.idx4;
+  p->kf.dt = (float)p->kd.dt;
+  p->kf.dth = (float)p->kd.dth;
+
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  int max_lds = 0;
+  e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipDeviceGetAttribute");
+  }
+  size_t lds = 0;
+  if (kind == SWEPT_HEAT_FTCS)
+    lds = dtype == SWEPT_F64 ? swept::phase_lds_bytes<swept::kHeat, double>(w)
+                             : swept::phase_lds_bytes<swept::kHeat, float>(w);
+  else
+    lds = dtype == SWEPT_F64 ? swept::phase_lds_bytes<swept::kKS, double>(w)
+                             : swept::phase_lds_bytes<swept::kKS, float>(w);
+  if (lds > (size_t)max_lds && !swept::wave_engine_supports(kind, w)) {
+    delete p;
+    return fail(SWEPT_EUNSUPPORTED, "tile too wide for the LDS of this device");
+  }
+  const size_t es = elem_size(dtype);
+  p->slots_bytes = (size_t)(2 * p->nt) * (size_t)swept::slot_values(w, p->s) * es;
+  p->buf_bytes = (size_t)n * es;
+  e = hipMalloc(&p->slots, p->slots_bytes);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(SWEPT_ENOMEM, std::string("hipMalloc(edge slots): ") + hipGetErrorString(e));
+  }
+  e = hipMalloc(&p->buf, p->buf_bytes);
+  if (e != hipSuccess) {
+    (void)hipFree(p->slots);
+    delete p;
+    return fail(SWEPT_ENOMEM, std::string("hipMalloc(naive buffer): ") + hipGetErrorString(e));
+  }
+  if (lds > (size_t)max_lds) p->engine = SWEPT_ENGINE_WAVE;
+  *out = p;
+  return SWEPT_OK;
+}
+
+int swept_plan_set_engine(swept_plan p, int engine) {
+  if (!p) return fail(SWEPT_EINVAL, "plan must not be NULL");
+  if (engine != SWEPT_ENGINE_AUTO && engine != SWEPT_ENGINE_LDS && engine != SWEPT_ENGINE_WAVE)
+    return fail(SWEPT_EINVAL, "unknown engine");
+  if (engine == SWEPT_ENGINE_WAVE && !swept::wave_engine_supports(p->kind, p->w))
+    return fail(SWEPT_EUNSUPPORTED, "no wave-resident kernel for this kind and tile width");
+  p->engine = engine;
+  return SWEPT_OK;
+}
+
+int swept_plan_info(swept_plan p, int* tile_width, int* steps_per_cycle, size_t* workspace_bytes) {
+  if (!p) return fail(SWEPT_EINVAL, "plan must not be NULL");
+  if (tile_width) *tile_width = p->w;
+  if (steps_per_cycle) *steps_per_cycle = p->h / tiers_per_step(p->kind);
+  if (workspace_bytes) *workspace_bytes = p->slots_bytes + p->buf_bytes;
+  return SWEPT_OK;
+}
+
+void swept_plan_destroy(swept_plan p) {
+  if (!p) return;
+  DeviceGuard g(p->device);
+  if (p->slots) (void)hipFree(p->slots);
+  if (p->buf) (void)hipFree(p->buf);
+  delete p;
+}
+
+int swept_run(swept_plan p, void* u, int64_t steps, void* stream) {
+  if (!p) return fail(SWEPT_EINVAL, "plan must not be NULL");
+  if (steps < 0) return fail(SWEPT_EINVAL, "steps must be >= 0");
+  if (steps == 0) return SWEPT_OK;
+  if (!u) return fail(SWEPT_EINVAL, "u must not be NULL");
+  std::vector<int32_t> e;
+  make_schedule(p->h, steps * tiers_per_step(p->kind), &e);
+  DeviceGuard g(p->device);
+  if (!g.ok) return hip_fail(g.err, "hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t nphase = (int64_t)e.size() + 1;
+  for (int64_t i = 0; i < nphase; ++i) {
+    PhaseArgs a;
+    a.u = u;
+    a.slots = p->slots;
+    a.n = p->n;
+    a.w = p->w;
+    a.nt = p->nt;
+    a.parity = (int)(i & 1);
+    a.hv = i == 0 ? 0 : e[(size_t)(i - 1)];
+    a.hl = i == nphase - 1 ? 0 : e[(size_t)i];
+    hipError_t err = p->dtype == SWEPT_F64 ? dispatch_phase<double>(p, a, p->kd, st)
+                                           : dispatch_phase<float>(p, a, p->kf, st);
+    if (err != hipSuccess) return hip_fail(err, "swept phase launch");
+  }
+  return SWEPT_OK;
+}
+
+int naive_run(swept_plan p, void* u, int64_t steps, void* stream) {
+  if (!p) return fail(SWEPT_EINVAL, "plan must not be NULL");
+  if (steps < 0) return fail(SWEPT_EINVAL, "steps must be >= 0");
+  if (steps == 0) return SWEPT_OK;
+  if (!u) return fail(SWEPT_EINVAL, "u must not be NULL");
+  DeviceGuard g(p->device);
+  if (!g.ok) return hip_fail(g.err, "hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t err = p->dtype == SWEPT_F64 ? run_naive<double>(p, static_cast<double*>(u), steps, p->kd, st)
+                                         : run_naive<float>(p, static_cast<float*>(u), steps, p->kf, st);
+  if (err != hipSuccess) return hip_fail(err, "naive launch");
+  return SWEPT_OK;
+}
+
+}  // extern "C"

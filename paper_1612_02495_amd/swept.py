@@ -1,0 +1,153 @@
+"""Python binding of the swept library: the C-ABI entry points under their own
+names, plus a small ``Plan`` convenience class.  PyTorch only supplies device
+memory (``Tensor.data_ptr()``) and the HIP stream; all arithmetic runs in the
+HIP kernels of libswept.so.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (SWEPT_ENGINE_AUTO, SWEPT_ENGINE_LDS, SWEPT_ENGINE_WAVE, SWEPT_F32, SWEPT_F64,
+                   SWEPT_HEAT_FTCS, SWEPT_KS_RK2, SweptError, check)
+
+KINDS = {"heat": SWEPT_HEAT_FTCS, "ks": SWEPT_KS_RK2}
+ENGINES = {"auto": SWEPT_ENGINE_AUTO, "lds": SWEPT_ENGINE_LDS, "wave": SWEPT_ENGINE_WAVE}
+
+
+def _kind(kind) -> int:
+    return KINDS[kind] if isinstance(kind, str) else int(kind)
+
+
+def _dtype_code(dtype) -> int:
+    import torch
+    if dtype in (torch.float64, np.float64, "f64", "float64", SWEPT_F64):
+        return SWEPT_F64
+    if dtype in (torch.float32, np.float32, "f32", "float32", SWEPT_F32):
+        return SWEPT_F32
+    raise ValueError(f"unsupported dtype {dtype!r}")
+
+
+def _stream_ptr(tensor, stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(tensor.device)
+    return ctypes.c_void_p(int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream))
+
+
+# --------------------------------------------------------- C-ABI names --
+
+def swept_plan_create(n: int, kind, dtype, dt: float, dx: float, alpha: float = 0.0,
+                      tile_width: int = 0, steps_per_cycle: int = 0) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    check(_lib.lib().swept_plan_create(ctypes.byref(h), int(n), _kind(kind), _dtype_code(dtype),
+                                       float(dt), float(dx), float(alpha), int(tile_width),
+                                       int(steps_per_cycle)))
+    return h
+
+
+def swept_run(plan, u, steps: int, stream=None) -> None:
+    check(_lib.lib().swept_run(plan, ctypes.c_void_p(u.data_ptr()), int(steps), _stream_ptr(u, stream)))
+
+
+def naive_run(plan, u, steps: int, stream=None) -> None:
+    check(_lib.lib().naive_run(plan, ctypes.c_void_p(u.data_ptr()), int(steps), _stream_ptr(u, stream)))
+
+
+def swept_plan_info(plan) -> dict:
+    w, spc, ws = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+    check(_lib.lib().swept_plan_info(plan, ctypes.byref(w), ctypes.byref(spc), ctypes.byref(ws)))
+    return {"tile_width": w.value, "steps_per_cycle": spc.value, "workspace_bytes": ws.value}
+
+
+def swept_plan_set_engine(plan, engine) -> None:
+    e = ENGINES[engine] if isinstance(engine, str) else int(engine)
+    check(_lib.lib().swept_plan_set_engine(plan, e))
+
+
+def swept_plan_destroy(plan) -> None:
+    if plan:
+        _lib.lib().swept_plan_destroy(plan)
+
+
+def swept_last_error() -> str:
+    return _lib.last_error()
+
+
+def swept_schedule(kind, tile_width: int, steps_per_cycle: int, steps: int) -> list[int]:
+    count = ctypes.c_int64()
+    check(_lib.lib().swept_schedule(_kind(kind), int(tile_width), int(steps_per_cycle), int(steps),
+                                    None, 0, ctypes.byref(count)))
+    buf = (ctypes.c_int32 * max(count.value, 1))()
+    check(_lib.lib().swept_schedule(_kind(kind), int(tile_width), int(steps_per_cycle), int(steps),
+                                    buf, count.value, ctypes.byref(count)))
+    return list(buf[: count.value])
+
+
+def swept_tile_geometry(kind, tile_width: int) -> dict:
+    t, r, e = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(_lib.lib().swept_tile_geometry(_kind(kind), int(tile_width), ctypes.byref(t),
+                                         ctypes.byref(r), ctypes.byref(e)))
+    return {"full_tiers": t.value, "row_values": r.value, "edge_slot_values": e.value}
+
+
+# ------------------------------------------------------------ wrapper --
+
+class Plan:
+    """Owns a swept plan; validates tensors before handing them to the C ABI."""
+
+    def __init__(self, n: int, kind, dtype, dt: float, dx: float, alpha: float = 0.0,
+                 tile_width: int = 0, steps_per_cycle: int = 0, engine=None):
+        import torch
+        self.n = int(n)
+        self.kind = _kind(kind)
+        self.dtype = torch.float64 if _dtype_code(dtype) == SWEPT_F64 else torch.float32
+        self._h = swept_plan_create(n, kind, dtype, dt, dx, alpha, tile_width, steps_per_cycle)
+        if engine is not None:
+            swept_plan_set_engine(self._h, engine)
+
+    def _check_tensor(self, u):
+        if not u.is_cuda:
+            raise ValueError("u must be a device tensor")
+        if u.dtype != self.dtype or u.numel() != self.n or not u.is_contiguous():
+            raise ValueError(f"u must be a contiguous {self.dtype} tensor of {self.n} elements")
+
+    def run(self, u, steps: int, stream=None):
+        self._check_tensor(u)
+        swept_run(self._h, u, steps, stream)
+        return u
+
+    def naive(self, u, steps: int, stream=None):
+        self._check_tensor(u)
+        naive_run(self._h, u, steps, stream)
+        return u
+
+    def set_engine(self, engine):
+        swept_plan_set_engine(self._h, engine)
+
+    def info(self) -> dict:
+        return swept_plan_info(self._h)
+
+    def close(self):
+        if self._h:
+            swept_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+__all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
+           "swept_plan_set_engine", "swept_plan_destroy", "swept_last_error", "swept_schedule",
+           "swept_tile_geometry"]

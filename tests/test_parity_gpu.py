@@ -1,0 +1,152 @@
+"""GPU parity: the swept path against the GPU naive path (bit for bit) and
+against the CPU oracle (bit for bit where the operation order is shared,
+otherwise within the stated tolerance), on seeded inputs through the C ABI.
+
+The swept rule reorders where and when the scheme is evaluated without
+changing it (arXiv 1612.02495, Sec. 2; the paper verifies KS by comparing
+swept against classic, Sec. 5), so equality with the naive kernel is exact.
+"""
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_02495_amd import Plan, inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12  # relative max-norm against the FP64 oracle
+
+
+def _dev(a, dtype):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _relmax(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _params(kind, n):
+    if kind == "heat":
+        dx = 1.0 / n
+        return dict(dt=0.3 * dx * dx, dx=dx, alpha=1.0)
+    return dict(dt=0.005, dx=0.5, alpha=0.0)
+
+
+def _oracle(kind, u0, prm, steps, np_dtype):
+    if kind == "heat":
+        return oracle.heat(u0, prm["alpha"], prm["dt"], prm["dx"], steps, dtype=np_dtype)
+    return oracle.ks(u0, prm["dt"], prm["dx"], steps, dtype=np_dtype)
+
+
+SMALL_CASES = [
+    # kind, n, w, steps_per_cycle, steps
+    ("heat", 16, 4, 0, 7),
+    ("heat", 16, 8, 0, 9),
+    ("heat", 32, 8, 3, 10),
+    ("heat", 64, 16, 0, 33),
+    ("heat", 32, 32, 0, 40),   # one tile: the diamond wraps onto itself
+    ("heat", 24, 8, 0, 13),    # n not a power of two
+    ("heat", 16, 4, 1, 5),
+    ("heat", 16, 4, 0, 1),     # fewer steps than one phase
+    ("heat", 256, 64, 0, 100),
+    ("heat", 1024, 128, 17, 301),
+    ("ks", 32, 8, 0, 5),
+    ("ks", 64, 16, 0, 9),
+    ("ks", 64, 16, 1, 7),
+    ("ks", 48, 16, 2, 11),
+    ("ks", 32, 32, 0, 12),
+    ("ks", 64, 8, 1, 3),
+    ("ks", 512, 64, 0, 40),
+    ("ks", 1024, 256, 5, 101),
+]
+
+
+@pytest.mark.parametrize("engine", ["lds", "auto"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind,n,w,spc,steps", SMALL_CASES)
+def test_swept_equals_naive_and_oracle_small(kind, n, w, spc, steps, dtype, engine):
+    rng = np.random.default_rng(zlib.crc32(repr((kind, n, w, spc, steps)).encode()))
+    u0 = rng.standard_normal(n)
+    prm = _params(kind, n)
+    plan = Plan(n, kind, dtype, prm["dt"], prm["dx"], prm["alpha"], tile_width=w, steps_per_cycle=spc,
+                engine=engine)
+    us = _dev(u0, dtype)
+    un = _dev(u0, dtype)
+    plan.run(us, steps)
+    plan.naive(un, steps)
+    s, nv = _host(us), _host(un)
+    assert np.array_equal(s, nv), f"max diff {np.max(np.abs(s - nv))}"
+    np_dtype = np.float64 if dtype == torch.float64 else np.float32
+    ref = _oracle(kind, u0.astype(np_dtype), prm, steps, np_dtype)
+    assert np.array_equal(s, ref), f"vs oracle rel {_relmax(s.astype(np.float64), ref.astype(np.float64))}"
+
+
+def test_heat_small_workload_fp64():
+    p = inputs.heat_small()
+    plan = Plan(p.n, "heat", torch.float64, p.dt, p.dx, p.alpha, tile_width=p.tile_width)
+    assert plan.info()["tile_width"] == 64 and plan.info()["steps_per_cycle"] == 32
+    us, un = _dev(p.u0, torch.float64), _dev(p.u0, torch.float64)
+    plan.run(us, p.steps)
+    plan.naive(un, p.steps)
+    s, nv = _host(us), _host(un)
+    assert np.array_equal(s, nv)
+    ref = oracle.heat(p.u0, p.alpha, p.dt, p.dx, p.steps)
+    assert _relmax(s, ref) <= F64_TOL
+    assert np.array_equal(s, ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_heat_large_grid_vs_oracle_1000_steps(dtype):
+    p = inputs.heat_large(steps=1000)
+    plan = Plan(p.n, "heat", dtype, p.dt, p.dx, p.alpha, tile_width=1024)
+    us = _dev(p.u0, dtype)
+    plan.run(us, p.steps)
+    s = _host(us).astype(np.float64)
+    ref64 = oracle.heat(p.u0, p.alpha, p.dt, p.dx, p.steps)
+    if dtype == torch.float64:
+        assert np.array_equal(s, ref64)
+    else:
+        ref32 = oracle.heat(p.u0.astype(np.float32), p.alpha, p.dt, p.dx, p.steps, dtype=np.float32)
+        assert np.array_equal(s, ref32.astype(np.float64))
+        err = _relmax(s, ref64)
+        print(f"FP32 heat N=2^20 T=1000 rel max-norm error vs FP64 oracle: {err:.3e}")
+        assert err < 1e-5
+
+
+def test_ks_grid_vs_oracle_1000_steps():
+    p = inputs.ks(n=2 ** 16, steps=1000)
+    plan = Plan(p.n, "ks", torch.float64, p.dt, p.dx, tile_width=1024)
+    us, un = _dev(p.u0, torch.float64), _dev(p.u0, torch.float64)
+    plan.run(us, p.steps)
+    plan.naive(un, p.steps)
+    s, nv = _host(us), _host(un)
+    assert np.array_equal(s, nv)
+    ref = oracle.ks(p.u0, p.dt, p.dx, p.steps)
+    assert np.array_equal(s, ref)
+
+
+def test_composition_and_noop():
+    p = inputs.heat_small()
+    plan = Plan(p.n, "heat", torch.float64, p.dt, p.dx, p.alpha, tile_width=64)
+    a, b = _dev(p.u0, torch.float64), _dev(p.u0, torch.float64)
+    plan.run(a, 300)
+    plan.run(a, 0)
+    plan.run(a, 700)
+    plan.run(b, 1000)
+    assert np.array_equal(_host(a), _host(b))
+
+
+def test_rejects_wrong_tensor():
+    plan = Plan(1024, "heat", torch.float64, 1e-7, 1e-3, 1.0, tile_width=64)
+    with pytest.raises(ValueError):
+        plan.run(torch.zeros(1024, dtype=torch.float32, device="cuda"), 1)
+    with pytest.raises(ValueError):
+        plan.run(torch.zeros(512, dtype=torch.float64, device="cuda"), 1)
