@@ -37,7 +37,9 @@ __device__ __forceinline__ void tier_update(T* __restrict__ dst, const T* __rest
   }
 }
 
-template <int KIND, typename T>
+// ROLE only names the launch for profilers (0 up-triangle, 1 diamond,
+// 2 down-triangle); the phase shape comes from hv and hl.
+template <int KIND, typename T, int ROLE>
 __global__ void __launch_bounds__(kLdsThreads)
 phase_lds_kernel(T* __restrict__ u, T* __restrict__ slots, int64_t n, int w, int64_t nt, int parity,
                  int hv, int hl, Consts<T> k) {
@@ -157,8 +159,10 @@ template <int KIND, typename T>
 hipError_t launch_phase_lds(const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
   const int threads = a.w >= kLdsThreads ? kLdsThreads : ((a.w + 63) / 64) * 64;
   const size_t lds = phase_lds_bytes<KIND, T>(a.w);
-  hipLaunchKernelGGL((phase_lds_kernel<KIND, T>), dim3((unsigned)a.nt), dim3(threads), lds, st,
-                     static_cast<T*>(a.u), static_cast<T*>(a.slots), a.n, a.w, a.nt, a.parity, a.hv, a.hl, k);
+  auto kern = a.hv == 0 ? phase_lds_kernel<KIND, T, 0>
+              : (a.hl == 0 ? phase_lds_kernel<KIND, T, 2> : phase_lds_kernel<KIND, T, 1>);
+  hipLaunchKernelGGL(kern, dim3((unsigned)a.nt), dim3(threads), lds, st, static_cast<T*>(a.u),
+                     static_cast<T*>(a.slots), a.n, a.w, a.nt, a.parity, a.hv, a.hl, k);
   return hipGetLastError();
 }
 

@@ -89,6 +89,51 @@ def test_swept_equals_naive_and_oracle_small(kind, n, w, spc, steps, dtype, engi
     assert np.array_equal(s, ref), f"vs oracle rel {_relmax(s.astype(np.float64), ref.astype(np.float64))}"
 
 
+WAVE_CASES = [
+    # kind, n, w (= 64 P), steps_per_cycle, steps
+    ("heat", 128, 128, 0, 70),       # P=2, one tile
+    ("heat", 384, 128, 0, 200),      # P=2, three tiles, remainder phase
+    ("heat", 512, 256, 0, 300),      # P=4
+    ("heat", 768, 256, 5, 77),       # P=4, short phases (trapezoids throughout)
+    ("heat", 1024, 512, 0, 520),     # P=8
+    ("heat", 2048, 1024, 0, 1500),   # P=16
+    ("heat", 2048, 1024, 0, 511),    # P=16, fewer steps than one phase
+    ("heat", 3072, 1024, 100, 1234),
+    ("ks", 512, 256, 0, 70),         # P=4
+    ("ks", 256, 256, 3, 29),         # P=4, one tile, short phases
+    ("ks", 1024, 512, 0, 150),       # P=8
+    ("ks", 2048, 1024, 0, 300),      # P=16
+    ("ks", 3072, 1024, 7, 61),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind,n,w,spc,steps", WAVE_CASES)
+def test_wave_engine_equals_naive_lds_and_oracle(kind, n, w, spc, steps, dtype):
+    rng = np.random.default_rng(zlib.crc32(repr(("wave", kind, n, w, spc, steps)).encode()))
+    u0 = rng.standard_normal(n)
+    prm = _params(kind, n)
+    plan = Plan(n, kind, dtype, prm["dt"], prm["dx"], prm["alpha"], tile_width=w, steps_per_cycle=spc,
+                engine="wave")
+    uw, un, ul = _dev(u0, dtype), _dev(u0, dtype), _dev(u0, dtype)
+    plan.run(uw, steps)
+    plan.naive(un, steps)
+    plan.set_engine("lds")
+    plan.run(ul, steps)
+    w_, n_, l_ = _host(uw), _host(un), _host(ul)
+    assert np.array_equal(w_, n_), f"wave vs naive max diff {np.max(np.abs(w_ - n_))}"
+    assert np.array_equal(l_, n_)
+    np_dtype = np.float64 if dtype == torch.float64 else np.float32
+    ref = _oracle(kind, u0.astype(np_dtype), prm, steps, np_dtype)
+    assert np.array_equal(w_, ref)
+
+
+def test_wave_engine_rejects_unsupported_width():
+    plan = Plan(3072, "heat", torch.float64, 1e-7, 1e-3, 1.0, tile_width=192)  # 192 = 64 * 3
+    with pytest.raises(Exception):
+        plan.set_engine("wave")
+
+
 def test_heat_small_workload_fp64():
     p = inputs.heat_small()
     plan = Plan(p.n, "heat", torch.float64, p.dt, p.dx, p.alpha, tile_width=p.tile_width)
