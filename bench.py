@@ -46,6 +46,36 @@ WORKLOADS = {
 }
 
 
+KERNEL_SOURCES = {
+    "wave": ["paper_1612_02495_amd/csrc/phase_wave.hip", "paper_1612_02495_amd/csrc/stencil.h",
+             "paper_1612_02495_amd/csrc/internal.h"],
+}
+TRAFFIC_SUMMARY = "profiles/phase_wave_heat_f64_n2p20_w1024_pmc.md"
+
+
+def _traffic_from_profile(wl, tile, engine):
+    """Calibrated HBM bytes per diamond launch from the committed rocprofv3
+    counter summary -- only if it covers this workload and the kernel source
+    has not changed since the counters were taken; otherwise None."""
+    import hashlib
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not (wl["kind"] == "heat" and wl["dtype"] == "f64" and wl["n"] == 2 ** 20 and tile == 1024
+            and engine in ("auto", "wave") and os.path.exists(path)):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", "|", "`")):
+            k, _, v = line.partition(":")
+            fields[k.strip()] = v.strip()
+    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in KERNEL_SOURCES["wave"])
+    if fields.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def _problem(wl):
     from paper_1612_02495_amd import inputs
     if wl["kind"] == "heat":
@@ -96,6 +126,10 @@ def main(argv=None):
     ap.add_argument("--no-naive", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle timesteps in the CPU sample")
+    ap.add_argument("--no-dominant", action="store_true",
+                    help="skip the per-launch timing of the diamond kernel (short profiler passes)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -118,6 +152,15 @@ def main(argv=None):
     T = wl["horizon"]
     u = torch.tensor(p.u0, dtype=tdtype, device="cuda")
 
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     for _ in range(args.warmup):
         plan.run(u, T)
     t_swept = _time_runs(lambda: plan.run(u, T), args.steps, torch)
@@ -127,31 +170,39 @@ def main(argv=None):
     # Dominant kernel (diamond phase): difference of two runs that differ only
     # in their number of full diamonds, timed with events on the launch stream.
     spc = info["steps_per_cycle"]
-    d_lo, d_hi = 1, 21
-    def run_d(d):
-        return lambda: plan.run(u, spc * (d + 1))
-    samples = []
-    for _ in range(3):
-        a = _time_runs(run_d(d_lo), 2, torch) / 2
-        b = _time_runs(run_d(d_hi), 2, torch) / 2
-        samples.append((b - a) / (d_hi - d_lo))
-    t_diamond = statistics.median(samples)
     tiers = spc * TIERS_PER_STEP[wl["kind"]]
     flops = FLOPS_PER_TIER_UPDATE[wl["kind"]] * p.n * tiers
-    achieved = flops / t_diamond / 1e12
+    t_diamond = None
+    achieved = None
+    if not args.no_dominant:
+        d_lo, d_hi = 1, 21
+
+        def run_d(d):
+            return lambda: plan.run(u, spc * (d + 1))
+        samples = []
+        for _ in range(3):
+            a = _time_runs(run_d(d_lo), 2, torch) / 2
+            b = _time_runs(run_d(d_hi), 2, torch) / 2
+            samples.append((b - a) / (d_hi - d_lo))
+        t_diamond = statistics.median(samples)
+        achieved = flops / t_diamond / 1e12
 
     naive = None
     if not args.no_naive:
         k_naive = args.naive_steps or args.steps
         v = torch.tensor(p.u0, dtype=tdtype, device="cuda")
-        plan.naive(v, min(T, 1000))
+        plan.naive(v, min(T, 100))
         t_naive = _time_runs(lambda: plan.naive(v, T), k_naive, torch)
+        bytes_per_update = (16 if wl["kind"] == "heat" else 40) // (1 if wl["dtype"] == "f64" else 2)
         naive = {"value": p.n * T * k_naive / t_naive, "ms_per_step": 1e3 * t_naive / k_naive,
-                 "ms_per_timestep": 1e3 * t_naive / (k_naive * T)}
+                 "ms_per_timestep": 1e3 * t_naive / (k_naive * T),
+                 "hbm_bound": {"bytes_per_cell_update": bytes_per_update,
+                               "achieved_GBps": bytes_per_update * p.n * T * k_naive / t_naive / 1e9,
+                               "peak_GBps": 8000.0}}
 
     cpu = None
     if not args.no_cpu_baseline:
-        budget = args.cpu_steps or (1500 if wl["kind"] == "heat" else 100)
+        budget = args.cpu_steps or (4000 if wl["kind"] == "heat" else 300)
         cpu = cpu_baseline(wl, budget)
 
     out = {
@@ -171,8 +222,11 @@ def main(argv=None):
                    "tile_width": info["tile_width"], "steps_per_cycle": spc, "engine": args.engine,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": "swept diamond phase", "achieved": achieved,
-                     "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS,
-                     "traffic": None, "launch_ms": 1e3 * t_diamond,
+                     "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": (achieved / ALU_PEAK_TFLOPS) if achieved else None,
+                     "traffic": _traffic_from_profile(wl, info["tile_width"], args.engine),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
+                     "launch_ms": (1e3 * t_diamond) if t_diamond else None,
                      "flops_per_launch": flops},
         "naive": naive,
         "speedup_vs_naive": (value / naive["value"]) if naive else None,
