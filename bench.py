@@ -37,11 +37,11 @@ TIERS_PER_STEP = {"heat": 1, "ks": 2}
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 WORKLOADS = {
-    "heat": dict(kind="heat", dtype="f64", n=2 ** 20, horizon=100000, tile=1024,
+    "heat": dict(kind="heat", dtype="f64", n=2 ** 20, horizon=100000, tile=0,
                  desc="heat FTCS periodic, N=2^20, FP64, Fo=1/4, 8-mode u0, 1e5 steps per run"),
-    "heat_f32": dict(kind="heat", dtype="f32", n=2 ** 20, horizon=100000, tile=1024,
+    "heat_f32": dict(kind="heat", dtype="f32", n=2 ** 20, horizon=100000, tile=0,
                      desc="heat FTCS periodic, N=2^20, FP32, Fo=1/4, 8-mode u0, 1e5 steps per run"),
-    "ks": dict(kind="ks", dtype="f64", n=2 ** 20, horizon=20000, tile=1024,
+    "ks": dict(kind="ks", dtype="f64", n=2 ** 20, horizon=20000, tile=0,
                desc="Kuramoto-Sivashinsky RK2 periodic, N=2^20, FP64, dx=0.5, dt=0.005, 2e4 steps per run"),
 }
 
@@ -120,7 +120,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="heat", choices=sorted(WORKLOADS))
     ap.add_argument("--engine", default="auto", choices=["auto", "lds", "wave"])
-    ap.add_argument("--tile", type=int, default=0, help="tile width (0 = workload default)")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="tile width (0 = run the autotuner and use its choice)")
     ap.add_argument("--horizon", type=int, default=0, help="timesteps per run (0 = workload default)")
     ap.add_argument("--naive-steps", type=int, default=0, help="timed naive runs (0 = same as --steps)")
     ap.add_argument("--no-naive", action="store_true")
@@ -147,7 +148,16 @@ def main(argv=None):
     tile = args.tile or wl["tile"]
     p = _problem(wl)
     tdtype = torch.float64 if wl["dtype"] == "f64" else torch.float32
-    plan = Plan(p.n, wl["kind"], tdtype, p.dt, p.dx, p.alpha, tile_width=tile, engine=args.engine)
+    tuned = None
+    if tile == 0:
+        # untimed plan setup: search tile width, phase height and engine on the real kernels
+        from paper_1612_02495_amd import swept_autotune
+        tuned = swept_autotune(p.n, wl["kind"], wl["dtype"], p.dt, p.dx, p.alpha)
+        plan = Plan(p.n, wl["kind"], tdtype, p.dt, p.dx, p.alpha, tile_width=tuned["tile_width"],
+                    steps_per_cycle=tuned["steps_per_cycle"], engine=tuned["engine"])
+        args.engine = tuned["engine"]
+    else:
+        plan = Plan(p.n, wl["kind"], tdtype, p.dt, p.dx, p.alpha, tile_width=tile, engine=args.engine)
     info = plan.info()
     T = wl["horizon"]
     u = torch.tensor(p.u0, dtype=tdtype, device="cuda")
@@ -220,7 +230,11 @@ def main(argv=None):
         "data": "synthetic (seeded; see paper_1612_02495_amd/inputs.py)",
         "config": {"workload": wl["desc"], "n": p.n, "timesteps_per_run": T, "kind": wl["kind"],
                    "tile_width": info["tile_width"], "steps_per_cycle": spc, "engine": args.engine,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "autotune": None if tuned is None else sorted(
+                       ({"w": c["tile_width"], "spc": c["steps_per_cycle"], "engine": c["engine"],
+                         "ns_per_update": round(c["ns_per_cell_update"], 6)} for c in tuned["candidates"]),
+                       key=lambda c: c["ns_per_update"])},
         "roofline": {"bound": "alu", "kernel": "swept diamond phase", "achieved": achieved,
                      "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / ALU_PEAK_TFLOPS) if achieved else None,

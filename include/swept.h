@@ -78,7 +78,11 @@ typedef struct swept_plan_s* swept_plan;
  *   dt, dx          timestep and grid spacing (finite, dx != 0).
  *   alpha           diffusivity (heat only; ignored for KS).
  *   tile_width      points per tile ("node", Sec. 4.2): a multiple of 2s
- *                   (s = 1 heat, 2 KS) and of 8 for KS, 4..4096; 0 picks one.
+ *                   (s = 1 heat, 2 KS) and of 8 for KS, 4..4096; 0 picks one:
+ *                   the autotuned configuration for (kind, dtype, n) when
+ *                   one is known (see swept_autotune; used only together with
+ *                   steps_per_cycle = 0), else the largest power of two up to
+ *                   1024 dividing n.
  *   steps_per_cycle timesteps per full phase: 1..w/2 (heat), 1..w/8 (KS);
  *                   0 = the pure triangle height (w/2 heat, w/8 KS).
  * Discretisation constants are formed once on the host in double and, for
@@ -150,6 +154,51 @@ int swept_schedule(int kind, int tile_width, int steps_per_cycle, int64_t steps,
  */
 int swept_tile_geometry(int kind, int tile_width, int* full_tiers, int* row_values,
                         int* edge_slot_values);
+
+/* ------------------------------------------------------------ autotuner -- */
+
+/* One timed candidate of swept_autotune. */
+typedef struct {
+  int32_t tile_width;
+  int32_t steps_per_cycle;
+  int32_t engine;   /* SWEPT_ENGINE_WAVE or SWEPT_ENGINE_LDS */
+  int32_t reserved; /* zero */
+  double ns_per_cell_update;
+} swept_tune_result;
+
+/*
+ * swept_autotune -- time the candidate configurations for a grid of n points
+ * and remember the fastest for (kind, dtype, n).  Candidates: every
+ * power-of-two tile width 64..2048 that divides n, each engine that has a
+ * kernel for it, and the full and half phase heights -- the per-size search
+ * of the best launch configuration of Sec. 5, extended to the swept
+ * parameters.  Each candidate runs `steps` timesteps (0 = 2048 heat / 512 KS;
+ * clamped to 4096 / 1024) on a library-owned zero grid, once to warm up and
+ * three times timed with HIP events on a library-owned stream; the best of
+ * the three counts.  Argument values dt, dx, alpha only feed the constants
+ * (timing does not depend on them).
+ *   results/cap/count  optional: every timed candidate (count = how many ran)
+ *   tile_width, steps_per_cycle, engine  optional: the winner
+ * The winner is stored in the process table and, if the environment variable
+ * SWEPT_AUTOTUNE_CACHE names a file, merged into that JSON file.  A later
+ * swept_plan_create with tile_width = 0 and steps_per_cycle = 0 for the same
+ * (kind, dtype, n) uses it.  Errors: EINVAL, EUNSUPPORTED (no width divides
+ * n), ENOMEM / EDEVICE.  Synchronous: returns after the timing finished.
+ */
+int swept_autotune(int64_t n, int kind, int dtype, double dt, double dx, double alpha, int64_t steps,
+                   swept_tune_result* results, int cap, int* count, int* tile_width, int* steps_per_cycle,
+                   int* engine);
+
+/*
+ * swept_autotune_lookup -- host-only: the remembered configuration for
+ * (kind, dtype, n) from the process table or the SWEPT_AUTOTUNE_CACHE file.
+ * EUNSUPPORTED when there is none.  Output pointers may be NULL.
+ */
+int swept_autotune_lookup(int64_t n, int kind, int dtype, int* tile_width, int* steps_per_cycle, int* engine,
+                          double* ns_per_cell_update);
+
+/* swept_autotune_forget -- host-only: clear the process table (files untouched). */
+void swept_autotune_forget(void);
 
 #ifdef __cplusplus
 }

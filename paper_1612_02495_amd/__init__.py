@@ -6,8 +6,9 @@ not load the library; the first call does.
 """
 from .swept import (Plan, SweptError, naive_run, swept_last_error, swept_plan_create,
                     swept_plan_destroy, swept_plan_info, swept_plan_set_engine, swept_run,
-                    swept_schedule, swept_tile_geometry)
+                    swept_schedule, swept_tile_geometry, swept_autotune, swept_autotune_lookup,
+                    swept_autotune_forget)
 
 __all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
            "swept_plan_set_engine", "swept_plan_destroy", "swept_last_error", "swept_schedule",
-           "swept_tile_geometry"]
+           "swept_tile_geometry", "swept_autotune", "swept_autotune_lookup", "swept_autotune_forget"]

@@ -31,6 +31,13 @@ _lock = threading.Lock()
 _lib = None
 
 
+class TuneResult(ctypes.Structure):
+    """swept_tune_result of include/swept.h."""
+    _fields_ = [("tile_width", ctypes.c_int32), ("steps_per_cycle", ctypes.c_int32),
+                ("engine", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ns_per_cell_update", ctypes.c_double)]
+
+
 class SweptError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"swept error {code}: {msg}")
@@ -52,8 +59,14 @@ def _declare(lib):
     lib.swept_schedule.argtypes = [i32, i32, i32, i64, ctypes.POINTER(ctypes.c_int32), i64,
                                    ctypes.POINTER(i64)]
     pi = ctypes.POINTER(i32)
+    pd = ctypes.POINTER(dbl)
     lib.swept_tile_geometry.argtypes = [i32, i32, pi, pi, pi]
-    for name in ("swept_tile_geometry", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
+    lib.swept_autotune.argtypes = [i64, i32, i32, dbl, dbl, dbl, i64, ctypes.POINTER(TuneResult), i32, pi,
+                                   pi, pi, pi]
+    lib.swept_autotune_lookup.argtypes = [i64, i32, i32, pi, pi, pi, pd]
+    lib.swept_autotune_forget.argtypes = []
+    lib.swept_autotune_forget.restype = None
+    for name in ("swept_autotune", "swept_autotune_lookup", "swept_tile_geometry", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
                  "swept_plan_set_engine", "swept_schedule"):
         getattr(lib, name).restype = i32
     return lib

@@ -9,6 +9,13 @@
 
 namespace swept {
 
+struct TuneEntry {
+  int tile_width = 0;
+  int steps_per_cycle = 0;
+  int engine = 0;
+  double ns_per_cell_update = 0.0;
+};
+
 // One swept phase over the whole ring (Sec. 4.2): every tile first fills the
 // V between the incoming edge bands (hv tiers; hv == 0 means "read the full
 // row from u"), then climbs the triangle/trapezoid Lambda (hl tiers; hl == 0
@@ -44,5 +51,10 @@ template <int KIND, typename T>
 hipError_t launch_phase_wave(const PhaseArgs& a, const Consts<T>& k, hipStream_t st);
 // Whether the wave-resident engine has a kernel for this kind and width.
 bool wave_engine_supports(int kind, int w);
+
+// Autotuner table (autotune.hip).
+bool tune_lookup(int kind, int dtype, int64_t n, TuneEntry* out);
+bool tune_store(int kind, int dtype, int64_t n, const TuneEntry& e);
+void tune_forget_all();
 
 }  // namespace swept

@@ -216,8 +216,20 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
   if (tile_width < 0) return fail(SWEPT_EINVAL, "tile_width must be >= 0");
   int w = tile_width;
   std::string why;
+  int tuned_engine = SWEPT_ENGINE_AUTO;
   if (w == 0) {
-    w = choose_tile(kind, n);
+    // tuned configuration for this (kind, dtype, n) if the autotuner has one
+    swept::TuneEntry te;
+    if (steps_per_cycle == 0 && swept::tune_lookup(kind, dtype, n, &te) && tile_ok(kind, te.tile_width, &why) &&
+        n % te.tile_width == 0 && te.steps_per_cycle >= 0 &&
+        te.steps_per_cycle * tiers_per_step(kind) <= full_tiers(kind, te.tile_width) &&
+        (te.engine != SWEPT_ENGINE_WAVE || swept::wave_engine_supports(kind, te.tile_width))) {
+      w = te.tile_width;
+      steps_per_cycle = te.steps_per_cycle;
+      tuned_engine = te.engine;
+    } else {
+      w = choose_tile(kind, n);
+    }
     if (w == 0) return fail(SWEPT_EUNSUPPORTED, "no supported tile width divides n");
   } else if (!tile_ok(kind, w, &why)) {
     return fail(SWEPT_EINVAL, why);
@@ -290,6 +302,7 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
     delete p;
     return fail(SWEPT_ENOMEM, std::string("hipMalloc(naive buffer): ") + hipGetErrorString(e));
   }
+  p->engine = tuned_engine;
   if (lds > (size_t)max_lds) p->engine = SWEPT_ENGINE_WAVE;
   *out = p;
   return SWEPT_OK;
@@ -360,6 +373,130 @@ int naive_run(swept_plan p, void* u, int64_t steps, void* stream) {
   hipError_t err = p->dtype == SWEPT_F64 ? run_naive<double>(p, static_cast<double*>(u), steps, p->kd, st)
                                          : run_naive<float>(p, static_cast<float*>(u), steps, p->kf, st);
   if (err != hipSuccess) return hip_fail(err, "naive launch");
+  return SWEPT_OK;
+}
+
+int swept_autotune_lookup(int64_t n, int kind, int dtype, int* tile_width, int* steps_per_cycle, int* engine,
+                          double* ns_per_cell_update) {
+  if (kind != SWEPT_HEAT_FTCS && kind != SWEPT_KS_RK2) return fail(SWEPT_EINVAL, "unknown stencil kind");
+  if (dtype != SWEPT_F32 && dtype != SWEPT_F64) return fail(SWEPT_EINVAL, "unknown dtype");
+  swept::TuneEntry te;
+  if (!swept::tune_lookup(kind, dtype, n, &te)) return fail(SWEPT_EUNSUPPORTED, "no tuned entry for this problem");
+  if (tile_width) *tile_width = te.tile_width;
+  if (steps_per_cycle) *steps_per_cycle = te.steps_per_cycle;
+  if (engine) *engine = te.engine;
+  if (ns_per_cell_update) *ns_per_cell_update = te.ns_per_cell_update;
+  return SWEPT_OK;
+}
+
+void swept_autotune_forget(void) { swept::tune_forget_all(); }
+
+int swept_autotune(int64_t n, int kind, int dtype, double dt, double dx, double alpha, int64_t steps,
+                   swept_tune_result* results, int cap, int* count, int* tile_width, int* steps_per_cycle,
+                   int* engine) {
+  if (kind != SWEPT_HEAT_FTCS && kind != SWEPT_KS_RK2) return fail(SWEPT_EINVAL, "unknown stencil kind");
+  if (dtype != SWEPT_F32 && dtype != SWEPT_F64) return fail(SWEPT_EINVAL, "unknown dtype");
+  if (n < kMinTile) return fail(SWEPT_EINVAL, "n must be >= 4");
+  if (steps < 0) return fail(SWEPT_EINVAL, "steps must be >= 0");
+  if (cap < 0 || (cap > 0 && !results)) return fail(SWEPT_EINVAL, "results must hold cap entries");
+  const int tps = tiers_per_step(kind);
+  // timed horizon: several full phases of the widest tile
+  int64_t T = steps > 0 ? steps : (kind == SWEPT_KS_RK2 ? 512 : 2048);
+  if (T > (kind == SWEPT_KS_RK2 ? 1024 : 4096)) T = kind == SWEPT_KS_RK2 ? 1024 : 4096;
+  struct Cand {
+    int w, spc, engine;
+  };
+  std::vector<Cand> cands;
+  std::string why;
+  for (int w = 64; w <= 2048; w <<= 1) {
+    if (n % w != 0 || n < w || !tile_ok(kind, w, &why)) continue;
+    const int full_steps = full_tiers(kind, w) / tps;
+    const int spcs[2] = {full_steps, full_steps / 2};
+    for (int eng : {SWEPT_ENGINE_WAVE, SWEPT_ENGINE_LDS}) {
+      if (eng == SWEPT_ENGINE_WAVE && !swept::wave_engine_supports(kind, w)) continue;
+      for (int si = 0; si < 2; ++si) {
+        if (spcs[si] < 1 || (si == 1 && spcs[1] == spcs[0])) continue;
+        cands.push_back({w, spcs[si], eng});
+      }
+    }
+  }
+  if (cands.empty()) return fail(SWEPT_EUNSUPPORTED, "no tile width divides n");
+
+  const size_t es = elem_size(dtype);
+  void* u = nullptr;
+  hipError_t e = hipMalloc(&u, (size_t)n * es);
+  if (e != hipSuccess) return fail(SWEPT_ENOMEM, std::string("hipMalloc(autotune grid): ") + hipGetErrorString(e));
+  e = hipMemset(u, 0, (size_t)n * es);
+  hipStream_t st = nullptr;
+  if (e == hipSuccess) e = hipStreamCreate(&st);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  if (e != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    if (st) (void)hipStreamDestroy(st);
+    (void)hipFree(u);
+    return hip_fail(e, "autotune setup");
+  }
+  int best = -1;
+  double best_ns = 0.0;
+  int nres = 0;
+  int rc = SWEPT_OK;
+  for (size_t ci = 0; ci < cands.size(); ++ci) {
+    const Cand& c = cands[ci];
+    swept_plan p = nullptr;
+    int r = swept_plan_create(&p, n, kind, dtype, dt, dx, alpha, c.w, c.spc);
+    if (r != SWEPT_OK) continue;  // e.g. LDS too small on this device
+    if (swept_plan_set_engine(p, c.engine) != SWEPT_OK) {
+      swept_plan_destroy(p);
+      continue;
+    }
+    float ms = 0.0f, best_ms = 0.0f;
+    r = swept_run(p, u, T, st);  // warm-up (code object load, caches)
+    for (int rep = 0; rep < 3 && r == SWEPT_OK; ++rep) {
+      e = hipEventRecord(t0, st);
+      if (e == hipSuccess) r = swept_run(p, u, T, st);
+      if (r == SWEPT_OK && e == hipSuccess) e = hipEventRecord(t1, st);
+      if (r == SWEPT_OK && e == hipSuccess) e = hipEventSynchronize(t1);
+      if (r == SWEPT_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+      if (e != hipSuccess) r = hip_fail(e, "autotune timing");
+      if (r == SWEPT_OK && (rep == 0 || ms < best_ms)) best_ms = ms;
+    }
+    swept_plan_destroy(p);
+    if (r != SWEPT_OK) {
+      rc = r;
+      break;
+    }
+    const double ns = 1e6 * (double)best_ms / ((double)n * (double)T);
+    if (nres < cap) {
+      results[nres].tile_width = c.w;
+      results[nres].steps_per_cycle = c.spc;
+      results[nres].engine = c.engine;
+      results[nres].reserved = 0;
+      results[nres].ns_per_cell_update = ns;
+    }
+    ++nres;
+    if (best < 0 || ns < best_ns) {
+      best = (int)ci;
+      best_ns = ns;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  (void)hipStreamDestroy(st);
+  (void)hipFree(u);
+  if (rc != SWEPT_OK) return rc;
+  if (best < 0) return fail(SWEPT_EUNSUPPORTED, "no candidate configuration could run");
+  if (count) *count = nres;
+  swept::TuneEntry te;
+  te.tile_width = cands[(size_t)best].w;
+  te.steps_per_cycle = cands[(size_t)best].spc;
+  te.engine = cands[(size_t)best].engine;
+  te.ns_per_cell_update = best_ns;
+  if (!swept::tune_store(kind, dtype, n, te)) return fail(SWEPT_EDEVICE, "could not write the autotune cache file");
+  if (tile_width) *tile_width = te.tile_width;
+  if (steps_per_cycle) *steps_per_cycle = te.steps_per_cycle;
+  if (engine) *engine = te.engine;
   return SWEPT_OK;
 }
 

@@ -93,6 +93,41 @@ def swept_tile_geometry(kind, tile_width: int) -> dict:
     return {"full_tiers": t.value, "row_values": r.value, "edge_slot_values": e.value}
 
 
+ENGINE_NAMES = {SWEPT_ENGINE_AUTO: "auto", SWEPT_ENGINE_LDS: "lds", SWEPT_ENGINE_WAVE: "wave"}
+
+
+def swept_autotune(n: int, kind, dtype, dt: float, dx: float, alpha: float = 0.0, steps: int = 0,
+                   max_results: int = 64) -> dict:
+    """Time the candidate configurations (device work, synchronous); returns the
+    winner and every timed candidate."""
+    res = (_lib.TuneResult * max_results)()
+    cnt, w, spc, eng = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(_lib.lib().swept_autotune(int(n), _kind(kind), _dtype_code(dtype), float(dt), float(dx),
+                                    float(alpha), int(steps), res, max_results, ctypes.byref(cnt),
+                                    ctypes.byref(w), ctypes.byref(spc), ctypes.byref(eng)))
+    cands = [{"tile_width": r.tile_width, "steps_per_cycle": r.steps_per_cycle,
+              "engine": ENGINE_NAMES[r.engine], "ns_per_cell_update": r.ns_per_cell_update}
+             for r in res[: min(cnt.value, max_results)]]
+    return {"tile_width": w.value, "steps_per_cycle": spc.value, "engine": ENGINE_NAMES[eng.value],
+            "candidates": cands}
+
+
+def swept_autotune_lookup(n: int, kind, dtype):
+    """Remembered configuration for (kind, dtype, n), or None."""
+    w, spc, eng, ns = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    rc = _lib.lib().swept_autotune_lookup(int(n), _kind(kind), _dtype_code(dtype), ctypes.byref(w),
+                                          ctypes.byref(spc), ctypes.byref(eng), ctypes.byref(ns))
+    if rc == _lib.SWEPT_EUNSUPPORTED:
+        return None
+    check(rc)
+    return {"tile_width": w.value, "steps_per_cycle": spc.value, "engine": ENGINE_NAMES[eng.value],
+            "ns_per_cell_update": ns.value}
+
+
+def swept_autotune_forget() -> None:
+    _lib.lib().swept_autotune_forget()
+
+
 # ------------------------------------------------------------ wrapper --
 
 class Plan:
@@ -150,4 +185,4 @@ class Plan:
 
 __all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
            "swept_plan_set_engine", "swept_plan_destroy", "swept_last_error", "swept_schedule",
-           "swept_tile_geometry"]
+           "swept_tile_geometry", "swept_autotune", "swept_autotune_lookup", "swept_autotune_forget"]
