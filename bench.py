@@ -43,7 +43,68 @@ WORKLOADS = {
                      desc="heat FTCS periodic, N=2^20, FP32, Fo=1/4, 8-mode u0, 1e5 steps per run"),
     "ks": dict(kind="ks", dtype="f64", n=2 ** 20, horizon=20000, tile=0,
                desc="Kuramoto-Sivashinsky RK2 periodic, N=2^20, FP64, dx=0.5, dt=0.005, 2e4 steps per run"),
+    "batch": dict(kind="heat", dtype="f64", n=0, horizon=5000, tile=0, batch=4096,
+                  desc="4096 independent periodic heat FTCS grids, N log-uniform in [2^8,2^16] "
+                       "(multiples of 16), Fo ~ U(0.05,0.45), FP64, 5000 steps, one persistent "
+                       "kernel per graph launch"),
+    "batch_ks": dict(kind="ks", dtype="f64", n=0, horizon=5000, tile=0, batch=4096,
+                     desc="4096 independent periodic KS grids, N log-uniform in [2^8,2^16] "
+                          "(multiples of 16), dx=0.5, dt=0.005, FP64, 5000 steps, one persistent "
+                          "kernel per graph launch"),
 }
+
+
+def run_batch(args, wl):
+    """Batched workload: one bench step = one graph launch of the persistent kernel."""
+    import numpy as np
+    import torch
+
+    from paper_1612_02495_amd import Batch, inputs
+    T = wl["horizon"]
+    probs = (inputs.heat_batch(nprob=wl["batch"], steps=T) if wl["kind"] == "heat"
+             else inputs.ks_batch(nprob=wl["batch"], steps=T))
+    n = np.array([p.n for p in probs])
+    b = Batch(n, wl["kind"], wl["dtype"], [p.dt for p in probs], [p.dx for p in probs],
+              [p.alpha for p in probs], T)
+    u = torch.tensor(np.concatenate([p.u0 for p in probs]), device="cuda")
+    for _ in range(args.warmup):
+        b.run(u)
+    t = _time_runs(lambda: b.run(u), args.steps, torch)
+    updates = int(n.sum()) * T * args.steps
+    tiers = TIERS_PER_STEP[wl["kind"]]
+    flops = FLOPS_PER_TIER_UPDATE[wl["kind"]] * int(n.sum()) * T * tiers
+    achieved = flops / (t / args.steps) / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        import time as _time
+        import oracle
+        budget = args.cpu_steps or 200
+        big = max(probs, key=lambda p: p.n)
+        t0 = _time.perf_counter()
+        for p in probs[:64]:
+            if wl["kind"] == "heat":
+                oracle.heat(p.u0, p.alpha, p.dt, p.dx, budget)
+            else:
+                oracle.ks(p.u0, p.dt, p.dx, budget)
+        el = _time.perf_counter() - t0
+        cells = sum(p.n for p in probs[:64]) * budget
+        cpu = {"value": cells / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+               "sample": f"first 64 of the {len(probs)} grids, {budget} of the {T} steps each "
+                         f"(largest grid in batch n={big.n}), single-thread C oracle, {el:.1f} s"}
+    return {
+        "metric": METRIC, "value": updates / t, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": wl["dtype"],
+        "data": "synthetic (seeded; see paper_1612_02495_amd/inputs.py)",
+        "config": {"workload": wl["desc"], "grids": int(n.size), "total_points": int(n.sum()),
+                   "timesteps_per_run": T, "kind": wl["kind"], "persistent_grid": b.grid,
+                   "edge_slot_bytes": b.workspace_bytes, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "kernel": "batched persistent swept kernel (whole launch)",
+                     "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": None,
+                     "launch_ms": 1e3 * t / args.steps, "flops_per_launch": flops},
+        "naive": None, "speedup_vs_naive": None, "cpu_baseline": cpu,
+    }
 
 
 KERNEL_SOURCES = {
@@ -145,6 +206,9 @@ def main(argv=None):
     wl = dict(WORKLOADS[args.workload])
     if args.horizon:
         wl["horizon"] = args.horizon
+    if wl.get("batch"):
+        print(json.dumps(run_batch(args, wl)))
+        return 0
     tile = args.tile or wl["tile"]
     p = _problem(wl)
     tdtype = torch.float64 if wl["dtype"] == "f64" else torch.float32

@@ -200,6 +200,52 @@ int swept_autotune_lookup(int64_t n, int kind, int dtype, int* tile_width, int* 
 /* swept_autotune_forget -- host-only: clear the process table (files untouched). */
 void swept_autotune_forget(void);
 
+/* -------------------------------------------------------------- batched -- */
+
+typedef struct swept_batch_s* swept_batch;
+
+/*
+ * swept_batch_create -- plan a batch of nprob independent periodic grids of
+ * uneven size, all of one kind and dtype, each advanced by `steps` timesteps
+ * per swept_batch_run.
+ *   n[i]                 points of grid i (host array): a multiple of 16,
+ *                        32 <= n[i] <= 2^30 (each lane of a wave holds 16
+ *                        points; other sizes fail with EUNSUPPORTED)
+ *   dt[i], dx[i], alpha[i]  per-grid parameters (host arrays; alpha is read
+ *                        for heat only and may be NULL for KS); constants are
+ *                        formed as in swept_plan_create
+ * The grids live back to back in one device array in input order (offsets
+ * from swept_batch_info).  Every grid is run with the swept rule of
+ * swept_run: wave-resident tiles of at most 1024 points with two halves of
+ * equal or neighbouring whole-lane widths (uneven tiles, flattened phases on
+ * the wider halves), zig-zag tilings, edge bands through HBM (Sec. 4.2-4.3).
+ * One persistent kernel runs the whole batch: each workgroup pulls the next
+ * grid, largest first, from a device counter and advances it through all of
+ * its phases.  The plan owns the edge slots, the grid descriptors and the
+ * counter.  Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE.
+ */
+int swept_batch_create(swept_batch* out, int32_t nprob, const int64_t* n, int kind, int dtype, const double* dt,
+                       const double* dx, const double* alpha, int64_t steps);
+
+/*
+ * swept_batch_run -- advance every grid of u (device, sum n[i] elements,
+ * in/out) by the plan's steps.  use_graph != 0: the counter reset and the
+ * persistent kernel are captured once into a HIP graph (re-captured when u
+ * changes) and replayed with one graph launch; use_graph == 0: the same two
+ * launches enqueued directly.  Asynchronous on `stream`.  Results equal
+ * naive_run / swept_run of each grid on its own, bit for bit.
+ */
+int swept_batch_run(swept_batch b, void* u, int use_graph, void* stream);
+
+/*
+ * swept_batch_info -- total points, per-grid offsets into u (host array of
+ * nprob entries, may be NULL), edge-slot bytes and persistent grid size.
+ */
+int swept_batch_info(swept_batch b, int64_t* total_points, int64_t* offsets, size_t* workspace_bytes, int* grid);
+
+/* swept_batch_destroy -- free the plan and its device memory (NULL is a no-op). */
+void swept_batch_destroy(swept_batch b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,8 +7,10 @@ not load the library; the first call does.
 from .swept import (Plan, SweptError, naive_run, swept_last_error, swept_plan_create,
                     swept_plan_destroy, swept_plan_info, swept_plan_set_engine, swept_run,
                     swept_schedule, swept_tile_geometry, swept_autotune, swept_autotune_lookup,
-                    swept_autotune_forget)
+                    swept_autotune_forget, Batch, swept_batch_create, swept_batch_run, swept_batch_info,
+                    swept_batch_destroy)
 
 __all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
            "swept_plan_set_engine", "swept_plan_destroy", "swept_last_error", "swept_schedule",
-           "swept_tile_geometry", "swept_autotune", "swept_autotune_lookup", "swept_autotune_forget"]
+           "swept_tile_geometry", "swept_autotune", "swept_autotune_lookup", "swept_autotune_forget",
+           "Batch", "swept_batch_create", "swept_batch_run", "swept_batch_info", "swept_batch_destroy"]

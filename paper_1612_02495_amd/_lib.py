@@ -66,7 +66,13 @@ def _declare(lib):
     lib.swept_autotune_lookup.argtypes = [i64, i32, i32, pi, pi, pi, pd]
     lib.swept_autotune_forget.argtypes = []
     lib.swept_autotune_forget.restype = None
-    for name in ("swept_autotune", "swept_autotune_lookup", "swept_tile_geometry", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
+    pl = ctypes.POINTER(i64)
+    lib.swept_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, pl, i32, i32, pd, pd, pd, i64]
+    lib.swept_batch_run.argtypes = [vp, vp, i32, vp]
+    lib.swept_batch_info.argtypes = [vp, pl, pl, ctypes.POINTER(sz), pi]
+    lib.swept_batch_destroy.argtypes = [vp]
+    lib.swept_batch_destroy.restype = None
+    for name in ("swept_batch_create", "swept_batch_run", "swept_batch_info", "swept_autotune", "swept_autotune_lookup", "swept_tile_geometry", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
                  "swept_plan_set_engine", "swept_schedule"):
         getattr(lib, name).restype = i32
     return lib

@@ -1,0 +1,371 @@
+// Batched swept runs: thousands of independent periodic grids of uneven size
+// advanced by one persistent kernel, launched as a captured HIP graph.
+//
+// Scheduling.  The grid of the persistent kernel is what the device holds
+// resident (occupancy x CUs).  Each workgroup takes the next problem from a
+// device-side counter -- problems are queued largest first, so the longest
+// jobs start early and the tail is short -- and runs all swept phases of that
+// problem itself: its NW waves share the problem's tiles within a phase and
+// meet at a workgroup barrier between phases.  No workgroup ever waits for
+// another, so every wave reaches the exit when the queue runs dry.
+//
+// Tiling of one problem of n points (n a multiple of P): the ring is c = n/P
+// lane-chunks, split into 2 nt halves of floor(c/2nt) or ceil(c/2nt) lanes
+// with nt = ceil(c/64), so every half is at most 32 lanes.  Even tile j is
+// halves (2j, 2j+1), odd tile j is halves (2j+1, 2j+2 mod 2nt): the zig-zag of
+// Sec. 4.2 with uneven tiles.  The phase height is the pure-triangle height of
+// the smallest half, floor(c/2nt) P / s tiers (even for KS); larger halves
+// carry a flat top.  The per-tile algorithm is wave_tile.h.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "swept.h"
+#include "wave_tile.h"
+
+namespace swept {
+namespace {
+
+constexpr int kBatchP = 16;  // points per lane
+constexpr int kBatchNW = 4;  // waves per workgroup
+
+template <typename T>
+struct BatchItem {
+  int64_t u_off;     // first point of this ring in the concatenated state
+  int64_t slot_off;  // first value of its 2 nt edge slots
+  int32_t n;         // ring points (multiple of P)
+  int32_t nt;        // tiles per tiling
+  int32_t h;         // tiers per full phase
+  int32_t pad;
+  Consts<T> k;
+};
+
+__global__ void batch_reset_kernel(int* queue) { *queue = 0; }
+
+template <int KIND, typename T, int P, int NW>
+__global__ void __launch_bounds__(64 * NW)
+batch_kernel(const BatchItem<T>* __restrict__ items, int nitems, T* u, T* slots, int64_t tiers, int* queue) {
+  constexpr int S = Radius<KIND>::value;
+  constexpr int SLEN = 64 * P + 2 * S;
+  __shared__ int s_item;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();  // every wave has read s_item before it is overwritten
+    if (it >= nitems) break;
+    const BatchItem<T> pr = items[it];
+    T* ring = u + pr.u_off;
+    T* slotA = slots + pr.slot_off;
+    T* slotB = slotA + (int64_t)pr.nt * SLEN;
+    const int c = pr.n / P;
+    const int halves = 2 * pr.nt;
+    const int hb = c / halves;
+    const int hx = c % halves;
+    const int64_t full = tiers / pr.h;
+    const int rem = (int)(tiers % pr.h);
+    const int64_t ne = full + (rem ? 1 : 0);  // edge sets; phases = ne + 1
+    for (int64_t ph = 0; ph <= ne; ++ph) {
+      const int hv = ph == 0 ? 0 : (ph - 1 < full ? pr.h : rem);
+      const int hl = ph == ne ? 0 : (ph < full ? pr.h : rem);
+      const int parity = (int)(ph & 1);
+      for (int j = wave; j < pr.nt; j += NW) {
+        const int iL = 2 * j + parity;
+        const int iR = (iL + 1) % halves;
+        wave::Tile<T> g;
+        g.origin = (int64_t)(iL * hb + min(iL, hx)) * P;
+        g.kL = hb + (iL < hx ? 1 : 0);
+        g.kR = hb + (iR < hx ? 1 : 0);
+        g.sL = parity ? slotB + (int64_t)j * SLEN : slotA + (int64_t)j * SLEN;
+        g.sR = parity ? slotA + (int64_t)((j + 1) % pr.nt) * SLEN : slotB + (int64_t)j * SLEN;
+        wave::tile_phase<KIND, T, P, 3>(ring, pr.n, g, hv, hl, pr.k, lane);
+      }
+      // the next phase's tiles read slots other waves of this group wrote
+      __threadfence();
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+  }
+}
+
+}  // namespace
+}  // namespace swept
+
+using swept::BatchItem;
+using swept::Consts;
+
+namespace {
+int bfail(int code, const std::string& m) { return swept::set_error(code, m); }
+int bhip(hipError_t e, const char* what) { return bfail(SWEPT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)); }
+}  // namespace
+
+struct swept_batch_s {
+  int kind = 0, dtype = 0;
+  int32_t nprob = 0;
+  int64_t steps = 0;
+  int64_t total_points = 0;
+  std::vector<int64_t> offsets;  // per problem, input order
+  void* items = nullptr;         // device BatchItem<T>[nprob], queue order
+  void* slots = nullptr;
+  size_t slots_bytes = 0;
+  int* queue = nullptr;
+  int device = 0;
+  int grid = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* graph_u = nullptr;
+};
+
+namespace {
+
+template <int KIND, typename T>
+void* batch_kernel_ptr() {
+  return reinterpret_cast<void*>(swept::batch_kernel<KIND, T, swept::kBatchP, swept::kBatchNW>);
+}
+
+void* kernel_for(int kind, int dtype) {
+  if (kind == SWEPT_HEAT_FTCS)
+    return dtype == SWEPT_F64 ? batch_kernel_ptr<swept::kHeat, double>() : batch_kernel_ptr<swept::kHeat, float>();
+  return dtype == SWEPT_F64 ? batch_kernel_ptr<swept::kKS, double>() : batch_kernel_ptr<swept::kKS, float>();
+}
+
+hipError_t enqueue_batch(swept_batch_s* b, void* u, hipStream_t st) {
+  hipLaunchKernelGGL(swept::batch_reset_kernel, dim3(1), dim3(1), 0, st, b->queue);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tiers = b->steps * (b->kind == SWEPT_KS_RK2 ? 2 : 1);
+  const dim3 grid((unsigned)b->grid), block(64 * swept::kBatchNW);
+  if (b->kind == SWEPT_HEAT_FTCS) {
+    if (b->dtype == SWEPT_F64)
+      hipLaunchKernelGGL((swept::batch_kernel<swept::kHeat, double, swept::kBatchP, swept::kBatchNW>), grid, block,
+                         0, st, static_cast<const BatchItem<double>*>(b->items), b->nprob, static_cast<double*>(u),
+                         static_cast<double*>(b->slots), tiers, b->queue);
+    else
+      hipLaunchKernelGGL((swept::batch_kernel<swept::kHeat, float, swept::kBatchP, swept::kBatchNW>), grid, block,
+                         0, st, static_cast<const BatchItem<float>*>(b->items), b->nprob, static_cast<float*>(u),
+                         static_cast<float*>(b->slots), tiers, b->queue);
+  } else {
+    if (b->dtype == SWEPT_F64)
+      hipLaunchKernelGGL((swept::batch_kernel<swept::kKS, double, swept::kBatchP, swept::kBatchNW>), grid, block,
+                         0, st, static_cast<const BatchItem<double>*>(b->items), b->nprob, static_cast<double*>(u),
+                         static_cast<double*>(b->slots), tiers, b->queue);
+    else
+      hipLaunchKernelGGL((swept::batch_kernel<swept::kKS, float, swept::kBatchP, swept::kBatchNW>), grid, block, 0,
+                         st, static_cast<const BatchItem<float>*>(b->items), b->nprob, static_cast<float*>(u),
+                         static_cast<float*>(b->slots), tiers, b->queue);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+Consts<T> consts_for(double dt, double dx, double alpha) {
+  // same host formulas as swept_plan_create (Sec. 4.1, Sec. 5)
+  const double fo = (alpha * dt) / (dx * dx);
+  const double idx2 = 1.0 / (dx * dx);
+  Consts<T> k;
+  k.fo = (T)fo;
+  k.c = (T)(1.0 - 2.0 * fo);
+  k.i4dx = (T)(1.0 / (4.0 * dx));
+  k.idx2 = (T)idx2;
+  k.idx4 = (T)(idx2 * idx2);
+  k.dt = (T)dt;
+  k.dth = (T)(0.5 * dt);
+  return k;
+}
+
+template <typename T>
+std::vector<BatchItem<T>> make_items(int kind, int32_t nprob, const int64_t* n, const double* dt, const double* dx,
+                                     const double* alpha, const std::vector<int32_t>& order,
+                                     const std::vector<int64_t>& offsets, size_t* slot_values) {
+  const int P = swept::kBatchP;
+  const int S = kind == SWEPT_KS_RK2 ? 2 : 1;
+  const int64_t slen = 64 * P + 2 * S;
+  std::vector<BatchItem<T>> items((size_t)nprob);
+  int64_t soff = 0;
+  for (int32_t q = 0; q < nprob; ++q) {
+    const int32_t i = order[(size_t)q];
+    BatchItem<T>& it = items[(size_t)q];
+    const int c = (int)(n[i] / P);
+    it.u_off = offsets[(size_t)i];
+    it.slot_off = soff;
+    it.n = (int32_t)n[i];
+    it.nt = (c + 63) / 64;
+    const int hb = c / (2 * it.nt);
+    int h = hb * P / S;
+    if (kind == SWEPT_KS_RK2) h &= ~1;
+    it.h = h;
+    it.pad = 0;
+    it.k = consts_for<T>(dt[i], dx[i], kind == SWEPT_HEAT_FTCS ? alpha[i] : 0.0);
+    soff += 2 * (int64_t)it.nt * slen;
+  }
+  *slot_values = (size_t)soff;
+  return items;
+}
+
+void batch_free(swept_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->items) (void)hipFree(b->items);
+  if (b->slots) (void)hipFree(b->slots);
+  if (b->queue) (void)hipFree(b->queue);
+  delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swept_batch_create(swept_batch* out, int32_t nprob, const int64_t* n, int kind, int dtype, const double* dt,
+                       const double* dx, const double* alpha, int64_t steps) {
+  if (!out) return bfail(SWEPT_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (kind != SWEPT_HEAT_FTCS && kind != SWEPT_KS_RK2) return bfail(SWEPT_EINVAL, "unknown stencil kind");
+  if (dtype != SWEPT_F32 && dtype != SWEPT_F64) return bfail(SWEPT_EINVAL, "unknown dtype");
+  if (nprob < 1) return bfail(SWEPT_EINVAL, "nprob must be >= 1");
+  if (!n || !dt || !dx || (kind == SWEPT_HEAT_FTCS && !alpha)) return bfail(SWEPT_EINVAL, "null host array");
+  if (steps < 0) return bfail(SWEPT_EINVAL, "steps must be >= 0");
+  const int P = swept::kBatchP;
+  for (int32_t i = 0; i < nprob; ++i) {
+    if (n[i] < 2 * P || n[i] % P != 0 || n[i] > (int64_t)1 << 30)
+      return bfail(SWEPT_EUNSUPPORTED, "problem " + std::to_string(i) +
+                                           ": n must be a multiple of 16, at least 32 and at most 2^30");
+    if (!std::isfinite(dt[i]) || !std::isfinite(dx[i]) || dx[i] == 0.0 ||
+        (kind == SWEPT_HEAT_FTCS && !std::isfinite(alpha[i])))
+      return bfail(SWEPT_EINVAL, "problem " + std::to_string(i) + ": dt, dx (and alpha) must be finite, dx != 0");
+  }
+  auto* b = new (std::nothrow) swept_batch_s();
+  if (!b) return bfail(SWEPT_ENOMEM, "host allocation failed");
+  b->kind = kind;
+  b->dtype = dtype;
+  b->nprob = nprob;
+  b->steps = steps;
+  b->offsets.resize((size_t)nprob);
+  int64_t off = 0;
+  for (int32_t i = 0; i < nprob; ++i) {
+    b->offsets[(size_t)i] = off;
+    off += n[i];
+  }
+  b->total_points = off;
+  // queue order: largest first (ties by input index)
+  std::vector<int32_t> order((size_t)nprob);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return n[x] > n[y]; });
+
+  hipError_t e = hipGetDevice(&b->device);
+  if (e != hipSuccess) {
+    delete b;
+    return bhip(e, "hipGetDevice");
+  }
+  size_t slot_values = 0;
+  size_t item_bytes = 0;
+  const void* host_items = nullptr;
+  std::vector<BatchItem<double>> id;
+  std::vector<BatchItem<float>> ifl;
+  if (dtype == SWEPT_F64) {
+    id = make_items<double>(kind, nprob, n, dt, dx, alpha, order, b->offsets, &slot_values);
+    host_items = id.data();
+    item_bytes = id.size() * sizeof(BatchItem<double>);
+  } else {
+    ifl = make_items<float>(kind, nprob, n, dt, dx, alpha, order, b->offsets, &slot_values);
+    host_items = ifl.data();
+    item_bytes = ifl.size() * sizeof(BatchItem<float>);
+  }
+  const size_t es = dtype == SWEPT_F64 ? sizeof(double) : sizeof(float);
+  b->slots_bytes = slot_values * es;
+  if ((e = hipMalloc(&b->items, item_bytes)) != hipSuccess || (e = hipMalloc(&b->slots, b->slots_bytes)) != hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void**>(&b->queue), sizeof(int))) != hipSuccess) {
+    batch_free(b);
+    return bfail(SWEPT_ENOMEM, std::string("hipMalloc(batch): ") + hipGetErrorString(e));
+  }
+  e = hipMemcpy(b->items, host_items, item_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    batch_free(b);
+    return bhip(e, "hipMemcpy(batch items)");
+  }
+  int per_cu = 0, cus = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(kind, dtype), 64 * swept::kBatchNW, 0);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e != hipSuccess) {
+    batch_free(b);
+    return bhip(e, "occupancy query");
+  }
+  if (per_cu < 1) per_cu = 1;
+  b->grid = (int)std::min<int64_t>((int64_t)per_cu * cus, nprob);
+  *out = b;
+  return SWEPT_OK;
+}
+
+int swept_batch_run(swept_batch b, void* u, int use_graph, void* stream) {
+  if (!b) return bfail(SWEPT_EINVAL, "batch must not be NULL");
+  if (!u) return bfail(SWEPT_EINVAL, "u must not be NULL");
+  if (b->steps == 0) return SWEPT_OK;
+  int prev = -1;
+  hipError_t e = hipGetDevice(&prev);
+  if (e != hipSuccess) return bhip(e, "hipGetDevice");
+  if (prev != b->device && (e = hipSetDevice(b->device)) != hipSuccess) return bhip(e, "hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = SWEPT_OK;
+  if (!use_graph) {
+    e = enqueue_batch(b, u, st);
+    if (e != hipSuccess) rc = bhip(e, "batch launch");
+  } else {
+    if (b->exec && b->graph_u != u) {
+      (void)hipGraphExecDestroy(b->exec);
+      (void)hipGraphDestroy(b->graph);
+      b->exec = nullptr;
+      b->graph = nullptr;
+    }
+    if (!b->exec) {
+      if (!b->cap_stream) e = hipStreamCreate(&b->cap_stream);
+      if (e == hipSuccess) e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        hipError_t le = enqueue_batch(b, u, b->cap_stream);
+        e = hipStreamEndCapture(b->cap_stream, &b->graph);
+        if (le != hipSuccess) e = le;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+        b->exec = nullptr;
+        rc = bhip(e, "batch graph capture");
+      } else {
+        b->graph_u = u;
+      }
+    }
+    if (rc == SWEPT_OK) {
+      e = hipGraphLaunch(b->exec, st);
+      if (e != hipSuccess) rc = bhip(e, "hipGraphLaunch");
+    }
+  }
+  if (prev != b->device) (void)hipSetDevice(prev);
+  return rc;
+}
+
+int swept_batch_info(swept_batch b, int64_t* total_points, int64_t* offsets, size_t* workspace_bytes, int* grid) {
+  if (!b) return bfail(SWEPT_EINVAL, "batch must not be NULL");
+  if (total_points) *total_points = b->total_points;
+  if (offsets) std::copy(b->offsets.begin(), b->offsets.end(), offsets);
+  if (workspace_bytes) *workspace_bytes = b->slots_bytes;
+  if (grid) *grid = b->grid;
+  return SWEPT_OK;
+}
+
+void swept_batch_destroy(swept_batch b) {
+  if (!b) return;
+  const int dev = b->device;
+  int prev = -1;
+  const bool ok = hipGetDevice(&prev) == hipSuccess;
+  if (ok && prev != dev) (void)hipSetDevice(dev);
+  batch_free(b);
+  if (ok && prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+}
+
+}  // extern "C"

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 #include "stencil.h"
 
@@ -51,6 +52,9 @@ template <int KIND, typename T>
 hipError_t launch_phase_wave(const PhaseArgs& a, const Consts<T>& k, hipStream_t st);
 // Whether the wave-resident engine has a kernel for this kind and width.
 bool wave_engine_supports(int kind, int w);
+
+// Record the calling thread's last error (swept_last_error) and return code.
+int set_error(int code, const std::string& msg);
 
 // Autotuner table (autotune.hip).
 bool tune_lookup(int kind, int dtype, int64_t n, TuneEntry* out);

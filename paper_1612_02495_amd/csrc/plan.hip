@@ -20,6 +20,12 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+}  // namespace
+
+int swept::set_error(int code, const std::string& msg) { return fail(code, msg); }
+
+namespace {
+
 int hip_fail(hipError_t e, const char* what) {
   return fail(SWEPT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }

@@ -95,11 +95,20 @@ def ks(n: int = 2 ** 16, seed: int = 2, steps: int = 20000) -> Problem:
     return Problem("ks", n, dt, dx, 0.0, steps, u0)
 
 
+def batch_sizes(rng: np.random.Generator, nprob: int, nmin_log2: float = 8.0, nmax_log2: float = 16.0,
+                quantum: int = 16) -> np.ndarray:
+    """N_p = quantum * round(2^U(nmin, nmax) / quantum): log-uniform sizes on the
+    lattice of whole register lanes (16 points per lane)."""
+    raw = 2.0 ** rng.uniform(nmin_log2, nmax_log2, size=nprob)
+    q = np.rint(raw / quantum).astype(np.int64) * quantum
+    return np.clip(q, int(2 ** nmin_log2), int(2 ** nmax_log2))
+
+
 def heat_batch(nprob: int = 4096, seed: int = 3, steps: int = 5000, nmin_log2: float = 8.0,
                nmax_log2: float = 16.0) -> list[Problem]:
     ss = np.random.SeedSequence(seed)
     top = np.random.default_rng(ss)
-    sizes = np.rint(2.0 ** top.uniform(nmin_log2, nmax_log2, size=nprob)).astype(np.int64)
+    sizes = batch_sizes(top, nprob, nmin_log2, nmax_log2)
     fos = top.uniform(0.05, 0.45, size=nprob)
     out = []
     for p, child in enumerate(ss.spawn(nprob)):
@@ -109,6 +118,23 @@ def heat_batch(nprob: int = 4096, seed: int = 3, steps: int = 5000, nmin_log2: f
         u0, ks_, amps = mode_sum(n, np.random.default_rng(child))
         out.append(Problem("heat", n, dt, dx, 1.0, steps, u0, modes=ks_, amps=amps,
                            extra={"fo_drawn": float(fos[p])}))
+    return out
+
+
+def ks_batch(nprob: int = 4096, seed: int = 6, steps: int = 5000, nmin_log2: float = 8.0,
+             nmax_log2: float = 16.0) -> list[Problem]:
+    """Independent periodic KS problems (dx = 0.5, dt = 0.005) of log-uniform size,
+    u0 = cos(x/16)(1 + sin(x/16)) + 1e-3 N(0,1) on each ring."""
+    ss = np.random.SeedSequence(seed)
+    top = np.random.default_rng(ss)
+    sizes = batch_sizes(top, nprob, nmin_log2, nmax_log2)
+    out = []
+    for p, child in enumerate(ss.spawn(nprob)):
+        n = int(sizes[p])
+        rng = np.random.default_rng(child)
+        x = np.arange(n, dtype=np.float64) * 0.5
+        u0 = np.cos(x / 16.0) * (1.0 + np.sin(x / 16.0)) + 1e-3 * rng.standard_normal(n)
+        out.append(Problem("ks", n, 0.005, 0.5, 0.0, steps, u0))
     return out
 
 

@@ -130,6 +130,77 @@ def swept_autotune_forget() -> None:
 
 # ------------------------------------------------------------ wrapper --
 
+# ------------------------------------------------------------- batched --
+
+def swept_batch_create(n, kind, dtype, dt, dx, alpha, steps: int) -> ctypes.c_void_p:
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    m = n.size
+    dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (m,)))
+    dx = np.ascontiguousarray(np.broadcast_to(np.asarray(dx, dtype=np.float64), (m,)))
+    alpha = np.ascontiguousarray(np.broadcast_to(np.asarray(alpha, dtype=np.float64), (m,)))
+    pd = ctypes.POINTER(ctypes.c_double)
+    h = ctypes.c_void_p()
+    check(_lib.lib().swept_batch_create(ctypes.byref(h), m, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        _kind(kind), _dtype_code(dtype), dt.ctypes.data_as(pd),
+                                        dx.ctypes.data_as(pd), alpha.ctypes.data_as(pd), int(steps)))
+    return h
+
+
+def swept_batch_run(batch, u, use_graph: bool = True, stream=None) -> None:
+    check(_lib.lib().swept_batch_run(batch, ctypes.c_void_p(u.data_ptr()), int(bool(use_graph)),
+                                     _stream_ptr(u, stream)))
+
+
+def swept_batch_info(batch, nprob: int) -> dict:
+    tot, ws, grid = ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_int()
+    offs = np.zeros(nprob, dtype=np.int64)
+    check(_lib.lib().swept_batch_info(batch, ctypes.byref(tot), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      ctypes.byref(ws), ctypes.byref(grid)))
+    return {"total_points": tot.value, "offsets": offs, "workspace_bytes": ws.value, "grid": grid.value}
+
+
+def swept_batch_destroy(batch) -> None:
+    if batch:
+        _lib.lib().swept_batch_destroy(batch)
+
+
+class Batch:
+    """Owns a batched plan: independent periodic grids stored back to back."""
+
+    def __init__(self, n, kind, dtype, dt, dx, alpha, steps: int):
+        import torch
+        self.n = np.asarray(n, dtype=np.int64).copy()
+        self.kind = _kind(kind)
+        self.dtype = torch.float64 if _dtype_code(dtype) == SWEPT_F64 else torch.float32
+        self.steps = int(steps)
+        self._h = swept_batch_create(self.n, kind, dtype, dt, dx, alpha, steps)
+        inf = swept_batch_info(self._h, self.n.size)
+        self.offsets = inf["offsets"]
+        self.total_points = inf["total_points"]
+        self.grid = inf["grid"]
+        self.workspace_bytes = inf["workspace_bytes"]
+
+    def run(self, u, use_graph: bool = True, stream=None):
+        if not u.is_cuda or u.dtype != self.dtype or u.numel() != self.total_points or not u.is_contiguous():
+            raise ValueError(f"u must be a contiguous device {self.dtype} tensor of {self.total_points} elements")
+        swept_batch_run(self._h, u, use_graph, stream)
+        return u
+
+    def split(self, u):
+        return [u[o:o + m] for o, m in zip(self.offsets, self.n)]
+
+    def close(self):
+        if self._h:
+            swept_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Plan:
     """Owns a swept plan; validates tensors before handing them to the C ABI."""
 
@@ -185,4 +256,5 @@ class Plan:
 
 __all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
            "swept_plan_set_engine", "swept_plan_destroy", "swept_last_error", "swept_schedule",
-           "swept_tile_geometry", "swept_autotune", "swept_autotune_lookup", "swept_autotune_forget"]
+           "swept_tile_geometry", "swept_autotune", "swept_autotune_lookup", "swept_autotune_forget",
+           "Batch", "swept_batch_create", "swept_batch_run", "swept_batch_info", "swept_batch_destroy"]

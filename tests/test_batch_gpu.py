@@ -1,0 +1,99 @@
+"""Batched persistent kernel on the GPU: every grid of the batch equals its
+own naive run (and the oracle) bit for bit; graph replays equal eager runs."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_02495_amd import Batch, Plan, inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _sizes(seed, m):
+    rng = np.random.default_rng(seed)
+    # uneven halves, one-tile rings, multi-tile rings, the 2^16 maximum
+    base = [32, 48, 256, 272, 1008, 1024, 1040, 2064, 4096, 5008, 65536]
+    extra = list(16 * rng.integers(2, 700, size=m - len(base)))
+    return np.array(base + extra, dtype=np.int64)
+
+
+def _batch_case(kind, dtype, steps, seed=0, m=40):
+    n = _sizes(seed, m)
+    rng = np.random.default_rng(seed + 100)
+    if kind == "heat":
+        dx = 1.0 / n
+        dt = rng.uniform(0.05, 0.45, size=n.size) * dx * dx
+        alpha = np.ones(n.size)
+    else:
+        dx = np.full(n.size, 0.5)
+        dt = np.full(n.size, 0.005)
+        alpha = np.zeros(n.size)
+    u0 = [rng.standard_normal(int(k)) for k in n]
+    return n, dt, dx, alpha, u0
+
+
+@pytest.mark.parametrize("kind,dtype,steps", [("heat", torch.float64, 300), ("heat", torch.float32, 129),
+                                              ("ks", torch.float64, 61)])
+def test_batch_equals_per_grid_naive_and_oracle(kind, dtype, steps):
+    n, dt, dx, alpha, u0 = _batch_case(kind, dtype, steps)
+    b = Batch(n, kind, dtype, dt, dx, alpha, steps)
+    u = torch.tensor(np.concatenate(u0), dtype=dtype, device="cuda")
+    b.run(u, use_graph=True)
+    torch.cuda.synchronize()
+    parts = [t.cpu().numpy() for t in b.split(u)]
+    np_dtype = np.float64 if dtype == torch.float64 else np.float32
+    for i in range(n.size):
+        plan = Plan(int(n[i]), kind, dtype, dt[i], dx[i], alpha[i], tile_width=16)
+        v = torch.tensor(u0[i], dtype=dtype, device="cuda")
+        plan.naive(v, steps)
+        torch.cuda.synchronize()
+        assert np.array_equal(parts[i], v.cpu().numpy()), f"grid {i} (n={n[i]}) differs from naive"
+        if n[i] <= 4096:
+            ref = (oracle.heat(u0[i].astype(np_dtype), alpha[i], dt[i], dx[i], steps, dtype=np_dtype)
+                   if kind == "heat" else oracle.ks(u0[i].astype(np_dtype), dt[i], dx[i], steps, dtype=np_dtype))
+            assert np.array_equal(parts[i], ref), f"grid {i} (n={n[i]}) differs from the oracle"
+
+
+def test_batch_graph_replays_match_eager():
+    n, dt, dx, alpha, u0 = _batch_case("heat", torch.float64, 200, seed=5, m=24)
+    b = Batch(n, "heat", torch.float64, dt, dx, alpha, 200)
+    state = torch.tensor(np.concatenate(u0), dtype=torch.float64, device="cuda")
+    g = torch.empty_like(state)
+    e = torch.empty_like(state)
+    for rep in range(3):
+        e.copy_(state)
+        b.run(e, use_graph=False)  # eager reference on its own buffer
+        torch.cuda.synchronize()
+        g.copy_(state)
+        b.run(g, use_graph=True)   # replay of the graph bound to g
+        torch.cuda.synchronize()
+        assert torch.equal(g, e), f"replay {rep} differs from eager"
+        state = e.clone() * 0.5 + 1.0  # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_batch_full_workload_sampled():
+    probs = inputs.heat_batch(nprob=4096, steps=5000)
+    n = np.array([p.n for p in probs])
+    dt = np.array([p.dt for p in probs])
+    dx = np.array([p.dx for p in probs])
+    b = Batch(n, "heat", torch.float64, dt, dx, np.ones(n.size), 5000)
+    u0 = np.concatenate([p.u0 for p in probs])
+    u = torch.tensor(u0, device="cuda")
+    b.run(u)
+    torch.cuda.synchronize()
+    host = u.cpu().numpy()
+    parts = [host[o:o + m] for o, m in zip(b.offsets, n)]
+    # property at every size: the ring sum is conserved (heat FTCS, periodic)
+    for i, p in enumerate(probs):
+        assert abs(parts[i].sum() - p.u0.sum()) <= 1e-9 * max(1.0, np.abs(p.u0).sum())
+    # sampled grids, smallest and largest included: bit for bit against naive
+    order = np.argsort(n)
+    pick = list(order[:3]) + list(order[-3:]) + list(np.random.default_rng(1).choice(n.size, 6, replace=False))
+    for i in pick:
+        plan = Plan(int(n[i]), "heat", torch.float64, dt[i], dx[i], 1.0, tile_width=16)
+        v = torch.tensor(probs[i].u0, device="cuda")
+        plan.naive(v, 5000)
+        torch.cuda.synchronize()
+        assert np.array_equal(parts[i], v.cpu().numpy()), f"grid {i} (n={n[i]})"
