@@ -246,6 +246,60 @@ int swept_batch_info(swept_batch b, int64_t* total_points, int64_t* offsets, siz
 /* swept_batch_destroy -- free the plan and its device memory (NULL is a no-op). */
 void swept_batch_destroy(swept_batch b);
 
+/* -------------------------------------------------------------- adjoint -- */
+
+typedef struct swept_adjoint_s* swept_adjoint;
+
+/*
+ * swept_adjoint_create -- plan the gradient of a functional of u_T for a
+ * batch of `batch` periodic heat FTCS grids of n points each (Eq. HeatDisc),
+ * all with the same dt, dx and number of steps, each with its own alpha.
+ *   dtype  SWEPT_F64 (other types fail with EUNSUPPORTED)
+ *   n      a positive multiple of 64
+ *   steps  >= 1
+ * The forward pass runs swept phases of 32 steps on tiles of 64 points and
+ * keeps the edge slots every phase writes (the swept state between
+ * launches) as checkpoints; the first steps mod 32 run with the classic
+ * scheme and keep their grids.  Workspace: about 2.06 n x 8 bytes per grid
+ * per phase of checkpoints, (steps mod 32 + 1) grids per grid of classic
+ * states, plus O(n) buffers -- all owned by the plan (swept_adjoint_info
+ * reports the checkpoint size).  Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE.
+ */
+int swept_adjoint_create(swept_adjoint* out, int32_t batch, int64_t n, int dtype, double dt, double dx,
+                         int64_t steps);
+
+/*
+ * swept_forward_ckpt -- u_T = A(alpha)^steps u_0 for every grid, storing the
+ * checkpoints the reverse sweep restarts from.  u0, uT: device, batch x n
+ * doubles, row-major (grid b at b*n), may not alias; alpha: device, batch
+ * doubles, read once here (Fo = (alpha dt)/(dx dx) per grid, as in
+ * swept_plan_create).  Asynchronous on `stream`.  The result equals
+ * swept_run / naive_run of each grid bit for bit.
+ */
+int swept_forward_ckpt(swept_adjoint a, const void* u0, const double* alpha, void* uT, void* stream);
+
+/*
+ * swept_adjoint_run -- reverse sweep after swept_forward_ckpt: given
+ * g_uT = dJ/du_T (device, batch x n), writes g_u0 = dJ/du_0 (device,
+ * batch x n) and g_alpha = dJ/dalpha (device, batch doubles).  For
+ * J = 1/2 ||u_T - y||^2, g_uT = u_T - y.  Each swept phase, last to first,
+ * is recomputed from its checkpointed edge slots in LDS and swept backwards
+ * (lambda_m = A lambda_{m+1}: A is symmetric) while dJ/dalpha accumulates
+ * lambda_{m+1} . (dt/dx^2)(u_{m,i-1} + u_{m,i+1} - 2 u_{m,i}); the sum is
+ * reduced in a fixed order (deterministic).  g_u0 equals steps applications
+ * of the forward stencil to g_uT, bit for bit.  Asynchronous on `stream`.
+ * EINVAL if no forward pass ran on this plan.
+ */
+int swept_adjoint_run(swept_adjoint a, const void* g_uT, void* g_u0, double* g_alpha, void* stream);
+
+/* swept_adjoint_info -- checkpoint bytes, tile width (64), steps per cycle
+ * (32) and the number of leading classic steps (steps mod 32). */
+int swept_adjoint_info(swept_adjoint a, size_t* checkpoint_bytes, int* tile_width, int* steps_per_cycle,
+                       int64_t* leading_classic_steps);
+
+/* swept_adjoint_destroy -- free the plan and its workspace (NULL is a no-op). */
+void swept_adjoint_destroy(swept_adjoint a);
+
 #ifdef __cplusplus
 }
 #endif

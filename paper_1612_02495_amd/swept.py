@@ -201,6 +201,116 @@ class Batch:
             pass
 
 
+# ------------------------------------------------------------- adjoint --
+
+def swept_adjoint_create(batch: int, n: int, dtype, dt: float, dx: float, steps: int) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    check(_lib.lib().swept_adjoint_create(ctypes.byref(h), int(batch), int(n), _dtype_code(dtype), float(dt),
+                                          float(dx), int(steps)))
+    return h
+
+
+def swept_forward_ckpt(adj, u0, alpha, uT, stream=None) -> None:
+    check(_lib.lib().swept_forward_ckpt(adj, ctypes.c_void_p(u0.data_ptr()), ctypes.c_void_p(alpha.data_ptr()),
+                                        ctypes.c_void_p(uT.data_ptr()), _stream_ptr(u0, stream)))
+
+
+def swept_adjoint_run(adj, g_uT, g_u0, g_alpha, stream=None) -> None:
+    check(_lib.lib().swept_adjoint_run(adj, ctypes.c_void_p(g_uT.data_ptr()), ctypes.c_void_p(g_u0.data_ptr()),
+                                       ctypes.c_void_p(g_alpha.data_ptr()), _stream_ptr(g_uT, stream)))
+
+
+def swept_adjoint_info(adj) -> dict:
+    cb, w, spc, r = ctypes.c_size_t(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+    check(_lib.lib().swept_adjoint_info(adj, ctypes.byref(cb), ctypes.byref(w), ctypes.byref(spc), ctypes.byref(r)))
+    return {"checkpoint_bytes": cb.value, "tile_width": w.value, "steps_per_cycle": spc.value,
+            "leading_classic_steps": r.value}
+
+
+def swept_adjoint_destroy(adj) -> None:
+    if adj:
+        _lib.lib().swept_adjoint_destroy(adj)
+
+
+class AdjointPlan:
+    """Checkpointed swept forward and reverse sweep for a batch of heat grids."""
+
+    def __init__(self, batch: int, n: int, dt: float, dx: float, steps: int):
+        self.batch, self.n, self.steps = int(batch), int(n), int(steps)
+        self._h = swept_adjoint_create(batch, n, "f64", dt, dx, steps)
+        self.info = swept_adjoint_info(self._h)
+
+    def _check(self, t, shape):
+        import torch
+        if not t.is_cuda or t.dtype != torch.float64 or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous float64 device tensor of shape {shape}")
+
+    def forward(self, u0, alpha, uT, stream=None):
+        self._check(u0, (self.batch, self.n))
+        self._check(alpha, (self.batch,))
+        self._check(uT, (self.batch, self.n))
+        swept_forward_ckpt(self._h, u0, alpha, uT, stream)
+        return uT
+
+    def adjoint(self, g_uT, g_u0, g_alpha, stream=None):
+        self._check(g_uT, (self.batch, self.n))
+        self._check(g_u0, (self.batch, self.n))
+        self._check(g_alpha, (self.batch,))
+        swept_adjoint_run(self._h, g_uT, g_u0, g_alpha, stream)
+        return g_u0, g_alpha
+
+    def close(self):
+        if self._h:
+            swept_adjoint_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _swept_heat_fn():
+    import torch
+
+    class SweptHeatFn(torch.autograd.Function):
+        """u_T = A(alpha)^steps u_0 for a batch of periodic heat grids (swept forward,
+        checkpointed); backward is the hand-written swept adjoint, returning
+        dJ/du_0 and dJ/dalpha."""
+
+        @staticmethod
+        def forward(ctx, u0, alpha, steps, dt, dx):
+            u0 = u0.contiguous()
+            alpha = alpha.contiguous()
+            plan = AdjointPlan(u0.shape[0], u0.shape[1], dt, dx, steps)
+            uT = torch.empty_like(u0)
+            plan.forward(u0, alpha, uT)
+            ctx.plan = plan
+            return uT
+
+        @staticmethod
+        def backward(ctx, g_uT):
+            plan = ctx.plan
+            g_u0 = torch.empty((plan.batch, plan.n), dtype=torch.float64, device=g_uT.device)
+            g_alpha = torch.empty((plan.batch,), dtype=torch.float64, device=g_uT.device)
+            plan.adjoint(g_uT.contiguous(), g_u0, g_alpha)
+            return g_u0, g_alpha, None, None, None
+
+    return SweptHeatFn
+
+
+_SWEPT_HEAT_FN = None
+
+
+def swept_heat(u0, alpha, steps: int, dt: float, dx: float):
+    """Differentiable swept heat run: u0 [batch, n] float64, alpha [batch] float64."""
+    global _SWEPT_HEAT_FN
+    if _SWEPT_HEAT_FN is None:
+        _SWEPT_HEAT_FN = _swept_heat_fn()
+    return _SWEPT_HEAT_FN.apply(u0, alpha, int(steps), float(dt), float(dx))
+
+
 class Plan:
     """Owns a swept plan; validates tensors before handing them to the C ABI."""
 
@@ -257,4 +367,6 @@ class Plan:
 __all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
            "swept_plan_set_engine", "swept_plan_destroy", "swept_last_error", "swept_schedule",
            "swept_tile_geometry", "swept_autotune", "swept_autotune_lookup", "swept_autotune_forget",
-           "Batch", "swept_batch_create", "swept_batch_run", "swept_batch_info", "swept_batch_destroy"]
+           "Batch", "swept_batch_create", "swept_batch_run", "swept_batch_info", "swept_batch_destroy",
+           "AdjointPlan", "swept_heat", "swept_adjoint_create", "swept_forward_ckpt", "swept_adjoint_run",
+           "swept_adjoint_info", "swept_adjoint_destroy"]

@@ -1,0 +1,27 @@
+"""Host-side validation of the adjoint ABI (no kernel runs)."""
+import ctypes
+
+import pytest
+
+from paper_1612_02495_amd import _lib
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 1024, 1, 1e-6, 1e-3, 100), _lib.SWEPT_EINVAL),        # batch
+    ((2, 1000, 1, 1e-6, 1e-3, 100), _lib.SWEPT_EUNSUPPORTED),  # n not a multiple of 64
+    ((2, 1024, 0, 1e-6, 1e-3, 100), _lib.SWEPT_EUNSUPPORTED),  # f32
+    ((2, 1024, 1, 1e-6, 1e-3, 0), _lib.SWEPT_EINVAL),          # steps
+    ((2, 1024, 1, 1e-6, 0.0, 10), _lib.SWEPT_EINVAL),          # dx
+])
+def test_adjoint_create_rejects(args, code):
+    h = ctypes.c_void_p()
+    assert _lib.lib().swept_adjoint_create(ctypes.byref(h), *args) == code
+    assert not h.value
+
+
+def test_adjoint_null_handles():
+    lib = _lib.lib()
+    assert lib.swept_forward_ckpt(None, None, None, None, None) == _lib.SWEPT_EINVAL
+    assert lib.swept_adjoint_run(None, None, None, None, None) == _lib.SWEPT_EINVAL
+    assert lib.swept_adjoint_info(None, None, None, None, None) == _lib.SWEPT_EINVAL
+    lib.swept_adjoint_destroy(None)

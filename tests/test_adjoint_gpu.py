@@ -1,0 +1,115 @@
+"""Swept adjoint on the GPU against the FP64 CPU reverse sweep, against
+steps applications of the forward stencil (bit for bit), and against central
+finite differences of the forward run."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_02495_amd import AdjointPlan, Plan, inputs, swept_heat
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,steps", [(64, 5), (64, 32), (128, 45), (256, 96), (192, 101), (512, 333)])
+def test_adjoint_matches_cpu_reverse_sweep(n, steps):
+    rng = np.random.default_rng(n * 1000 + steps)
+    batch = 3
+    dx = 1.0 / n
+    dt = dx * dx
+    alpha = rng.uniform(0.05, 0.45, size=batch)
+    u0 = rng.standard_normal((batch, n))
+    y = rng.standard_normal((batch, n))
+    plan = AdjointPlan(batch, n, dt, dx, steps)
+    du0 = torch.tensor(u0, device="cuda")
+    dal = torch.tensor(alpha, device="cuda")
+    uT = torch.empty_like(du0)
+    plan.forward(du0, dal, uT)
+    g_uT = uT - torch.tensor(y, device="cuda")
+    g_u0 = torch.empty_like(du0)
+    g_a = torch.empty_like(dal)
+    plan.adjoint(g_uT.contiguous(), g_u0, g_a)
+    torch.cuda.synchronize()
+    uT_h, g_h, ga_h, guT_h = uT.cpu().numpy(), g_u0.cpu().numpy(), g_a.cpu().numpy(), g_uT.cpu().numpy()
+    for b in range(batch):
+        ref_uT = oracle.heat(u0[b], alpha[b], dt, dx, steps)
+        assert np.array_equal(uT_h[b], ref_uT)
+        J, g, ga = oracle.heat_adjoint(u0[b], y[b], alpha[b], dt, dx, steps)
+        assert np.array_equal(g_h[b], g), f"grid {b}: max |dJ/du0 diff| {np.max(np.abs(g_h[b] - g))}"
+        assert abs(ga_h[b] - ga) <= 1e-12 * abs(ga), (ga_h[b], ga)
+        # dJ/du0 = A^steps g_uT: the forward naive kernel on g_uT, bit for bit
+        p = Plan(n, "heat", torch.float64, dt, dx, alpha[b], tile_width=64)
+        v = torch.tensor(guT_h[b], device="cuda")
+        p.naive(v, steps)
+        torch.cuda.synchronize()
+        assert np.array_equal(v.cpu().numpy(), g_h[b])
+
+
+def test_autograd_function_and_gradcheck():
+    n, steps, batch = 64, 40, 2
+    dx = 1.0 / n
+    dt = dx * dx
+    rng = np.random.default_rng(5)
+    u0 = torch.tensor(rng.standard_normal((batch, n)), device="cuda", requires_grad=True)
+    alpha = torch.tensor(rng.uniform(0.1, 0.4, size=batch), device="cuda", requires_grad=True)
+    y = torch.tensor(rng.standard_normal((batch, n)), device="cuda")
+    uT = swept_heat(u0, alpha, steps, dt, dx)
+    J = 0.5 * ((uT - y) ** 2).sum()
+    J.backward()
+    for b in range(batch):
+        Jb, g, ga = oracle.heat_adjoint(u0[b].detach().cpu().numpy(), y[b].cpu().numpy(),
+                                        alpha[b].item(), dt, dx, steps)
+        assert np.array_equal(u0.grad[b].cpu().numpy(), g)
+        assert abs(alpha.grad[b].item() - ga) <= 1e-12 * abs(ga)
+    f = lambda a, b: swept_heat(a, b, steps, dt, dx)
+    assert torch.autograd.gradcheck(f, (u0.detach().requires_grad_(), alpha.detach().requires_grad_()),
+                                    eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+def test_adjoint_full_size_central_differences():
+    # N = 2^18, T = 10^4 heat grids of the adjoint workload (two of its 64 grids)
+    u0s, alpha, u0t, alpha_t, dt, dx, steps = inputs.heat_adjoint(batch=2)
+    n = u0s.shape[1]
+    # target from a perturbed forward run
+    y = np.empty_like(u0t)
+    for b in range(2):
+        p = Plan(n, "heat", torch.float64, dt, dx, alpha_t[b], tile_width=1024)
+        v = torch.tensor(u0t[b], device="cuda")
+        p.run(v, steps)
+        torch.cuda.synchronize()
+        y[b] = v.cpu().numpy()
+    plan = AdjointPlan(2, n, dt, dx, steps)
+    du0 = torch.tensor(u0s, device="cuda")
+    dal = torch.tensor(alpha, device="cuda")
+    uT = torch.empty_like(du0)
+    plan.forward(du0, dal, uT)
+    dy = torch.tensor(y, device="cuda")
+    g_u0 = torch.empty_like(du0)
+    g_a = torch.empty_like(dal)
+    plan.adjoint((uT - dy).contiguous(), g_u0, g_a)
+    torch.cuda.synchronize()
+
+    def J(b, u, a):
+        p = Plan(n, "heat", torch.float64, dt, dx, a, tile_width=1024)
+        v = torch.tensor(u, device="cuda")
+        p.run(v, steps)
+        torch.cuda.synchronize()
+        return 0.5 * math.fsum(((v.cpu().numpy() - y[b]) ** 2).tolist())
+
+    h = 1e-6   # step on alpha
+    hu = 1e-2  # J is exactly quadratic in u0: a central difference has no truncation error,
+    # and a larger step keeps the round-off of J (about 1e-11) far below the 1e-6 bar
+    rng = np.random.default_rng(9)
+    for b in range(2):
+        fd = (J(b, u0s[b], alpha[b] + h) - J(b, u0s[b], alpha[b] - h)) / (2 * h)
+        ga = g_a[b].item()
+        print(f"grid {b}: dJ/dalpha swept {ga:.12e} central FD {fd:.12e} rel {abs(fd - ga) / abs(ga):.2e}")
+        assert abs(fd - ga) <= 1e-6 * abs(ga), (b, fd, ga)
+        d = rng.standard_normal(n)
+        d /= np.linalg.norm(d)
+        fdu = (J(b, u0s[b] + hu * d, alpha[b]) - J(b, u0s[b] - hu * d, alpha[b])) / (2 * hu)
+        gd = float(np.dot(g_u0[b].cpu().numpy(), d))
+        print(f"grid {b}: dJ/du0 . d swept {gd:.12e} central FD {fdu:.12e}")
+        assert abs(fdu - gd) <= 1e-6 * max(abs(gd), 1e-12), (b, fdu, gd)
