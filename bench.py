@@ -51,7 +51,66 @@ WORKLOADS = {
                      desc="4096 independent periodic KS grids, N log-uniform in [2^8,2^16] "
                           "(multiples of 16), dx=0.5, dt=0.005, FP64, 5000 steps, one persistent "
                           "kernel per graph launch"),
+    "adjoint": dict(kind="heat", dtype="f64", n=2 ** 18, horizon=10000, tile=64, adjoint=64,
+                    desc="gradient of J = 1/2 ||u_T - y||^2 w.r.t. u0 and alpha for 64 periodic heat "
+                         "FTCS grids, N=2^18, FP64, 1e4 steps: checkpointed swept forward + swept "
+                         "adjoint (one bench step = forward + reverse)"),
 }
+
+
+def run_adjoint(args, wl):
+    """Adjoint workload: one bench step = swept_forward_ckpt + swept_adjoint_run."""
+    import numpy as np
+    import torch
+
+    from paper_1612_02495_amd import AdjointPlan, inputs
+    B = args.batch or wl["adjoint"]
+    T = wl["horizon"]
+    u0, alpha, u0t, alpha_t, dt, dx, _ = inputs.heat_adjoint(batch=B, n=wl["n"], steps=T)
+    n = u0.shape[1]
+    plan = AdjointPlan(B, n, dt, dx, T)
+    du0 = torch.tensor(u0, device="cuda")
+    dal = torch.tensor(alpha, device="cuda")
+    # the target: a forward run from the perturbed initial states and alphas
+    y = torch.empty_like(du0)
+    plan.forward(torch.tensor(u0t, device="cuda"), torch.tensor(alpha_t, device="cuda"), y)
+    uT = torch.empty_like(du0)
+    g_u0 = torch.empty_like(du0)
+    g_a = torch.empty_like(dal)
+
+    def step():
+        plan.forward(du0, dal, uT)
+        g = uT - y
+        plan.adjoint(g, g_u0, g_a)
+
+    for _ in range(args.warmup):
+        step()
+    t = _time_runs(step, args.steps, torch)
+    t_fwd = _time_runs(lambda: plan.forward(du0, dal, uT), args.steps, torch)
+    updates = B * n * T * args.steps
+    cpu = None
+    if not args.no_cpu_baseline:
+        import time as _time
+        import oracle
+        cs = args.cpu_steps or 100
+        t0 = _time.perf_counter()
+        oracle.heat_adjoint(u0[0], u0t[0], alpha[0], dt, dx, cs)
+        el = _time.perf_counter() - t0
+        cpu = {"value": n * cs / el, "unit": "cell-updates/s of gradient (forward + reverse)", "cores": 1,
+               "kind": "oracle", "sample": f"one of the {B} grids, {cs} of the {T} steps, single-thread C "
+                                           f"checkpointed reverse sweep, {el:.1f} s"}
+    return {
+        "metric": METRIC, "value": updates / t, "unit": "cell-updates/s of gradient (forward + reverse)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded; see paper_1612_02495_amd/inputs.py)",
+        "config": {"workload": wl["desc"], "batch": B, "n": n, "timesteps": T,
+                   "adjoint_grad_ms": 1e3 * t / args.steps, "forward_ckpt_ms": 1e3 * t_fwd / args.steps,
+                   "checkpoint_bytes": plan.info["checkpoint_bytes"],
+                   "tile_width": plan.info["tile_width"], "steps_per_cycle": plan.info["steps_per_cycle"],
+                   "leading_classic_steps": plan.info["leading_classic_steps"], "parallelism": "single GPU"},
+        "roofline": None, "naive": None, "speedup_vs_naive": None, "cpu_baseline": cpu,
+    }
 
 
 def run_batch(args, wl):
@@ -190,6 +249,7 @@ def main(argv=None):
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle timesteps in the CPU sample")
     ap.add_argument("--no-dominant", action="store_true",
                     help="skip the per-launch timing of the diamond kernel (short profiler passes)")
+    ap.add_argument("--batch", type=int, default=0, help="grids in the adjoint workload (0 = 64)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args(argv)
@@ -208,6 +268,9 @@ def main(argv=None):
         wl["horizon"] = args.horizon
     if wl.get("batch"):
         print(json.dumps(run_batch(args, wl)))
+        return 0
+    if wl.get("adjoint"):
+        print(json.dumps(run_adjoint(args, wl)))
         return 0
     tile = args.tile or wl["tile"]
     p = _problem(wl)
