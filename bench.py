@@ -239,7 +239,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=5, help="timed bench steps (swept runs)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="heat", choices=sorted(WORKLOADS))
-    ap.add_argument("--engine", default="auto", choices=["auto", "lds", "wave"])
+    ap.add_argument("--engine", default="auto", choices=["auto", "lds", "wave", "compact"])
     ap.add_argument("--tile", type=int, default=0,
                     help="tile width (0 = run the autotuner and use its choice)")
     ap.add_argument("--horizon", type=int, default=0, help="timesteps per run (0 = workload default)")

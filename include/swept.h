@@ -67,6 +67,9 @@ extern "C" {
 #define SWEPT_ENGINE_AUTO 0 /* wave-resident engine where it applies, else LDS */
 #define SWEPT_ENGINE_LDS 1  /* tile in LDS, two tier rows, one thread block    */
 #define SWEPT_ENGINE_WAVE 2 /* tile in the registers of one wave64, DPP halos   */
+#define SWEPT_ENGINE_COMPACT 3 /* wave64 per tile, V/Lambda compacted onto the
+                                  lanes: R points per lane as the part grows or
+                                  shrinks, bands in LDS                         */
 
 typedef struct swept_plan_s* swept_plan;
 
@@ -118,9 +121,12 @@ int swept_plan_info(swept_plan p, int* tile_width, int* steps_per_cycle, size_t*
 
 /*
  * swept_plan_set_engine -- choose the kernel that runs the phases:
- * SWEPT_ENGINE_AUTO, _LDS or _WAVE.  _WAVE requires tile_width = 64*P with
- * P in {2, 4, 8, 16, 32} for heat and {4, 8, 16} for KS; otherwise the call
- * fails with EUNSUPPORTED and the plan keeps its engine.
+ * SWEPT_ENGINE_AUTO, _LDS, _WAVE or _COMPACT.  _WAVE requires tile_width =
+ * 64*P with P in {2, 4, 8, 16} for heat and {4, 8, 16} for KS; _COMPACT
+ * requires P in {8, 16} for either kind; otherwise the call fails with
+ * EUNSUPPORTED and the plan keeps its engine.  Every engine computes the
+ * same values bit for bit and leaves the same edge slots, so the choice
+ * changes only the speed.
  */
 int swept_plan_set_engine(swept_plan p, int engine);
 
@@ -161,7 +167,7 @@ int swept_tile_geometry(int kind, int tile_width, int* full_tiers, int* row_valu
 typedef struct {
   int32_t tile_width;
   int32_t steps_per_cycle;
-  int32_t engine;   /* SWEPT_ENGINE_WAVE or SWEPT_ENGINE_LDS */
+  int32_t engine;   /* SWEPT_ENGINE_LDS, _WAVE or _COMPACT */
   int32_t reserved; /* zero */
   double ns_per_cell_update;
 } swept_tune_result;

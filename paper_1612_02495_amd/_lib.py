@@ -26,6 +26,7 @@ SWEPT_F64 = 1
 SWEPT_ENGINE_AUTO = 0
 SWEPT_ENGINE_LDS = 1
 SWEPT_ENGINE_WAVE = 2
+SWEPT_ENGINE_COMPACT = 3
 
 _lock = threading.Lock()
 _lib = None

@@ -1,0 +1,360 @@
+// One swept phase of one 64-lane tile with the active region compacted onto
+// fewer points per lane (the compacted wave engine).
+//
+// The swept rule's V part grows from nothing to the full tile and its
+// Lambda part shrinks back (Sec. 4.2), so a wave that always spans the whole
+// tile leaves about half of its lanes on don't-care points.  Here the part of
+// the tile that a run of tiers touches is laid out over all 64 lanes with R
+// contiguous points per lane, R = step, 2 step, .., P (step 2 for the 3-point
+// stencil, 4 for the 5-point one so that every layout holds whole KS step
+// pairs).  A layout R covers the 64 R points centred on the tile middle,
+// x in [32 (P - R), 32 (P + R)).  The V part starts in the narrowest layout
+// and widens as its gap grows, the Lambda part starts in the full layout and
+// narrows as its triangle climbs; each change of layout passes the live row
+// through LDS.  Within one layout the tier code is the register engine's
+// (wave_tile.h) on a 64-lane tile with its seam at lane 32.
+//
+// The edge bands live in LDS for the whole phase, position-major
+// sb[(x + S) * 2 + (tier & 1)] for x in [-S, 64 P + S): the incoming slots
+// are copied in before the V part and the outgoing slots copied out after the
+// Lambda part, so the slot contents are exactly those of the register engine
+// and both engines can run alternate phases of one run.  Each layout loads
+// the band values of its own points into registers (V) or merges the values
+// its tiers collect back into LDS (Lambda).
+#pragma once
+
+#include "wave_tile.h"
+
+namespace swept {
+namespace compact {
+
+// LDS index with one spare value every 32, which spreads lane-strided
+// accesses over more banks.
+__host__ __device__ constexpr int pad(int i) { return i + (i >> 5); }
+
+template <int KIND>
+struct Step {
+  static constexpr int value = Radius<KIND>::value == 1 ? 2 : 4;
+};
+
+// LDS values of the band buffer and of the relayout staging row.
+template <int KIND, int P>
+struct Lds {
+  static constexpr int S = Radius<KIND>::value;
+  static constexpr int band = pad(2 * (64 * P + 2 * S) - 1) + 1;
+  static constexpr int stage = pad(64 * P - 1) + 1;
+};
+
+// V tiers of block b in a layout of R points per lane whose seam is at lane
+// 32: all B tiers (FULL) or those below t1.  Left band of tier t:
+// [-S(t+2), -S t) from the seam, lanes 31-b and 30-b; right band
+// [S t, S(t+2)), lanes 32+b and 33+b.
+template <int KIND, typename T, int R, bool FULL, bool TIPS>
+__device__ __forceinline__ void v_blk(T (&A)[R], T (&Q)[R], const T (&buf)[R][2], int b, int t1, int lane,
+                                      const T (&tipL)[Radius<KIND>::value],
+                                      const T (&tipR)[Radius<KIND>::value], const Consts<T>& k) {
+  constexpr int S = Radius<KIND>::value;
+  constexpr int B = R / S;
+  const bool mL0 = lane == 31 - b, mL1 = lane == 30 - b;
+  const bool mR0 = lane == 32 + b, mR1 = lane == 33 + b;
+  const bool first = lane == 0, last = lane == 63;
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    const int t = b * B + j;
+    if (FULL || t < t1) {
+      T(&row)[R] = KIND == kHeat ? A : wave::row_of<T, R>(A, Q, j & 1);
+#pragma unroll
+      for (int i = 0; i < 2 * S; ++i) {
+        const int ol = R - S * (j + 2) + i;  // offset from lane 31-b
+        const int rl = (ol + R) % R;
+        row[rl] = wave::pick(ol < 0 ? mL1 : mL0, buf[rl][j & 1], row[rl]);
+        const int orr = S * j + i;  // offset from lane 32+b
+        const int rr = orr % R;
+        row[rr] = wave::pick(orr >= R ? mR1 : mR0, buf[rr][j & 1], row[rr]);
+      }
+      wave::tier<KIND, T, R, TIPS>(A, Q, ((j + 1) & 1) != 0, tipL, tipR, first, last, k);
+    }
+  }
+}
+
+// V tiers [t0, t1) with t0 a multiple of the block height: whole blocks, then
+// the guarded remainder (with the triangle tips when TIPS).
+template <int KIND, typename T, int R, bool TIPS>
+__device__ __forceinline__ void v_run(T (&A)[R], T (&Q)[R], const T (&buf)[R][2], int t0, int t1, int lane,
+                                      const T (&tipL)[Radius<KIND>::value],
+                                      const T (&tipR)[Radius<KIND>::value], const Consts<T>& k) {
+  constexpr int B = R / Radius<KIND>::value;
+  if (t0 >= t1) return;
+  const int bl = (t1 - 1) / B;  // block holding the last tier
+  for (int b = t0 / B; b < bl; ++b) v_blk<KIND, T, R, true, false>(A, Q, buf, b, t1, lane, tipL, tipR, k);
+  v_blk<KIND, T, R, false, TIPS>(A, Q, buf, bl, t1, lane, tipL, tipR, k);
+}
+
+// Lambda tiers of block b, counted from the base of the layout's own 64 R-
+// point tile: all B tiers (FULL) or those below t1.  Each collects the band
+// values of tier t ([S t, S t + 2S), lanes b and b+1; [64 R - S(t+2),
+// 64 R - S t), lanes 63-b and 62-b), then computes tier t+1 unless
+// t == tskip (the empty top of a full triangle; never inside a FULL block).
+template <int KIND, typename T, int R, bool FULL>
+__device__ __forceinline__ void l_blk(T (&A)[R], T (&Q)[R], T (&buf)[R][2], int b, int t1, int tskip, int lane,
+                                      const Consts<T>& k) {
+  constexpr int S = Radius<KIND>::value;
+  constexpr int B = R / S;
+  const bool mL0 = lane == b, mL1 = lane == b + 1;
+  const bool mR0 = lane == 63 - b, mR1 = lane == 62 - b;
+  const T tip0[S] = {};
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    const int t = b * B + j;
+    if (FULL || t < t1) {
+      T(&row)[R] = KIND == kHeat ? A : wave::row_of<T, R>(A, Q, j & 1);
+#pragma unroll
+      for (int i = 0; i < 2 * S; ++i) {
+        const int ol = S * j + i;  // offset from lane b
+        const int rl = ol % R;
+        buf[rl][j & 1] = wave::pick(ol >= R ? mL1 : mL0, row[rl], buf[rl][j & 1]);
+        const int orr = R - S * (j + 2) + i;  // offset from lane 63-b
+        const int rr = (orr + R) % R;
+        buf[rr][j & 1] = wave::pick(orr < 0 ? mR1 : mR0, row[rr], buf[rr][j & 1]);
+      }
+      if (FULL || t != tskip)
+        wave::tier<KIND, T, R, false>(A, Q, ((j + 1) & 1) != 0, tip0, tip0, false, false, k);
+    }
+  }
+}
+
+// Lambda tiers [0, t1) of a layout: whole blocks, then the guarded remainder.
+template <int KIND, typename T, int R>
+__device__ __forceinline__ void l_run(T (&A)[R], T (&Q)[R], T (&buf)[R][2], int t1, int tskip, int lane,
+                                      const Consts<T>& k) {
+  constexpr int B = R / Radius<KIND>::value;
+  if (t1 <= 0) return;
+  const int bl = (t1 - 1) / B;
+  for (int b = 0; b < bl; ++b) l_blk<KIND, T, R, true>(A, Q, buf, b, t1, -1, lane, k);
+  l_blk<KIND, T, R, false>(A, Q, buf, bl, t1, tskip, lane, k);
+}
+
+// V layouts R, R + step, .., P - step.  `done` counts the V tiers already
+// computed; the row travels between layouts through stg.
+template <int KIND, typename T, int P, int R>
+__device__ __forceinline__ void v_narrow(T* sb, T* stg, int hv, int& done, int lane, const Consts<T>& k) {
+  if constexpr (R < P) {
+    constexpr int S = Radius<KIND>::value;
+    // The layout holds the tiers whose band fits, S (t + 2) <= 32 R; it hands
+    // over on a block boundary of the next layout (for KS an even tier).
+    constexpr int BN = (R + Step<KIND>::value) / S;
+    constexpr int kEnd = (32 * R / S - 1) / BN * BN;
+    const int tend = hv < kEnd ? hv : kEnd;
+    if (done < tend) {
+      const int xl = 32 * (P - R) + lane * R;
+      T A[R], Q[R], buf[R][2];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        A[r] = done > 0 ? stg[pad(xl + r)] : T(0);
+        Q[r] = T(0);
+        buf[r][0] = sb[pad(2 * (xl + r + S))];
+        buf[r][1] = sb[pad(2 * (xl + r + S) + 1)];
+      }
+      const T tip0[S] = {};
+      v_run<KIND, T, R, false>(A, Q, buf, done, tend, lane, tip0, tip0, k);
+      done = tend;
+      __syncthreads();  // every lane has read its row before the row is rewritten
+#pragma unroll
+      for (int r = 0; r < R; ++r) stg[pad(xl + r)] = A[r];
+      __syncthreads();
+    }
+    v_narrow<KIND, T, P, R + Step<KIND>::value>(sb, stg, hv, done, lane, k);
+  }
+}
+
+// Lambda layouts R, R - step, .., step, entered at tier `done` (a multiple of
+// 32 step / S, where the triangle first fits the next narrower layout).
+template <int KIND, typename T, int P, int R>
+__device__ __forceinline__ void l_narrow(T* sb, T* stg, int hl, bool empty_top, int& done, int lane,
+                                         const Consts<T>& k) {
+  if constexpr (R > 0) {
+    constexpr int S = Radius<KIND>::value;
+    constexpr int ST = Step<KIND>::value;
+    constexpr int kFirst = 32 * (P - R) / S;  // first tier of this layout
+    constexpr int kNext = R > ST ? 32 * (P - R + ST) / S : 1 << 30;
+    if (done < hl) {
+      const int tend = hl < kNext ? hl : kNext;
+      const int xl = 32 * (P - R) + lane * R;
+      T A[R], Q[R], buf[R][2];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        A[r] = stg[pad(xl + r)];
+        Q[r] = T(0);
+        buf[r][0] = sb[pad(2 * (xl + r + S))];
+        buf[r][1] = sb[pad(2 * (xl + r + S) + 1)];
+      }
+      // entered at its first tier (done == kFirst): virtual tiers from 0
+      const int tskip = empty_top ? hl - 1 - kFirst : -1;
+      l_run<KIND, T, R>(A, Q, buf, tend - kFirst, tskip, lane, k);
+      done = tend;
+      if (done >= hl && !empty_top) {
+        // flat top of the trapezoid: the row at its top tier
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int x = xl + r;
+          if (x >= S * hl && x < 64 * P - S * hl) {
+            if (hl & 1)
+              buf[r][1] = A[r];
+            else
+              buf[r][0] = A[r];
+          }
+        }
+      }
+      __syncthreads();  // all reads of this layout's rows precede the writes
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        sb[pad(2 * (xl + r + S))] = buf[r][0];
+        sb[pad(2 * (xl + r + S) + 1)] = buf[r][1];
+        if (done < hl) stg[pad(xl + r)] = A[r];
+      }
+      __syncthreads();
+    }
+    l_narrow<KIND, T, P, R - ST>(sb, stg, hl, empty_top, done, lane, k);
+  }
+}
+
+// ROLE: 0 up-triangle (hv == 0), 1 diamond, 2 down-triangle (hl == 0).  The
+// tile is 64 P points from `origin`, seam at 32 P; sL/sR are its left and
+// right edge slots (layout as in wave_tile.h with kL = kR = 32).
+template <int KIND, typename T, int P, int ROLE>
+__device__ __forceinline__ void tile_phase(T* u, int64_t n, int64_t origin, T* sL, T* sR, int hv, int hl,
+                                           const Consts<T>& k, int lane, T* sb, T* stg) {
+  constexpr int S = Radius<KIND>::value;
+  constexpr int B = P / S;
+  constexpr int W = 64 * P;
+  constexpr int HALF = 32 * P;
+  constexpr int ST = Step<KIND>::value;
+  constexpr int SV = 2 * (HALF + S);  // values of one slot that a phase reads or writes
+
+  T A[P];
+  T Q[P];
+  T buf[P][2];
+#pragma unroll
+  for (int r = 0; r < P; ++r) Q[r] = T(0);
+
+  if constexpr (ROLE == 0) {
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      int64_t g2 = origin + lane * P + r;
+      if (g2 >= n) g2 -= n;
+      A[r] = u[g2];
+    }
+  } else {
+    // incoming slots: consumer left input p = x + S, right input p = x - HALF;
+    // every load is issued before the first LDS store
+    {
+      constexpr int NIT = (SV + 63) / 64;
+      T inL[NIT], inR[NIT];
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int i = it * 64 + lane;
+        inL[it] = i < SV ? sL[i] : T(0);
+        inR[it] = i < SV ? sR[i] : T(0);
+      }
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int i = it * 64 + lane;
+        if (i < SV) {
+          sb[pad(i)] = inL[it];
+          sb[pad(SV + i)] = inR[it];
+        }
+      }
+    }
+    __syncthreads();
+    int done = 0;
+    v_narrow<KIND, T, P, ST>(sb, stg, hv, done, lane, k);
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      A[r] = done > 0 ? stg[pad(lane * P + r)] : T(0);
+      buf[r][0] = sb[pad(2 * (lane * P + r + S))];
+      buf[r][1] = sb[pad(2 * (lane * P + r + S) + 1)];
+    }
+    // triangle tips beyond the tile ends, used by the last tier of a full V
+    T tipL[S], tipR[S];
+    const int tp = (hv - 1) & 1;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      tipL[i] = sb[pad(2 * i + tp)];
+      tipR[i] = sb[pad(2 * (W + S + i) + tp)];
+    }
+    v_run<KIND, T, P, true>(A, Q, buf, done, hv, lane, tipL, tipR, k);
+    // flat tops of the producer trapezoids: tile points outside the gap
+    if (S * hv < HALF) {
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        const int x = lane * P + r;
+        if (x < HALF - S * hv || x >= HALF + S * hv) A[r] = wave::pick((hv & 1) != 0, buf[r][1], buf[r][0]);
+      }
+    }
+    __syncthreads();  // the V's reads of sb and stg precede the Lambda's writes
+  }
+
+  if constexpr (ROLE == 2) {
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      int64_t g2 = origin + lane * P + r;
+      if (g2 >= n) g2 -= n;
+      u[g2] = A[r];
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      buf[r][0] = T(0);
+      buf[r][1] = T(0);
+    }
+    const bool empty_top = 2 * S * hl >= W;
+    constexpr int kNext = P > ST ? 32 * ST / S : 1 << 30;
+    const int tend = hl < kNext ? hl : kNext;
+    const int tskip = empty_top ? hl - 1 : -1;
+    l_run<KIND, T, P>(A, Q, buf, tend, tskip, lane, k);
+    int done = tend;
+    if (done >= hl && !empty_top) {
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        const int x = lane * P + r;
+        if (x >= S * hl && x < W - S * hl) {
+          if (hl & 1)
+            buf[r][1] = A[r];
+          else
+            buf[r][0] = A[r];
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      sb[pad(2 * (lane * P + r + S))] = buf[r][0];
+      sb[pad(2 * (lane * P + r + S) + 1)] = buf[r][1];
+      if (done < hl) stg[pad(lane * P + r)] = A[r];
+    }
+    __syncthreads();
+    l_narrow<KIND, T, P, P - ST>(sb, stg, hl, empty_top, done, lane, k);
+    // outgoing slots: producer left side p = x (x < HALF + S), right side
+    // p = x - HALF + S (x >= HALF - S)
+    {
+      constexpr int NIT = (SV + 63) / 64;
+      T outL[NIT], outR[NIT];
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int i = it * 64 + lane;
+        outL[it] = i < SV ? sb[pad(2 * S + i)] : T(0);
+        outR[it] = i < SV ? sb[pad(2 * HALF + i)] : T(0);
+      }
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int i = it * 64 + lane;
+        if (i < SV) {
+          sL[i] = outL[it];
+          sR[i] = outR[it];
+        }
+      }
+    }
+  }
+}
+
+}  // namespace compact
+}  // namespace swept

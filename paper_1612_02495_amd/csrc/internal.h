@@ -53,6 +53,11 @@ hipError_t launch_phase_wave(const PhaseArgs& a, const Consts<T>& k, hipStream_t
 // Whether the wave-resident engine has a kernel for this kind and width.
 bool wave_engine_supports(int kind, int w);
 
+template <int KIND, typename T>
+hipError_t launch_phase_compact(const PhaseArgs& a, const Consts<T>& k, hipStream_t st);
+// Whether the compacted wave engine has a kernel for this kind and width.
+bool compact_engine_supports(int kind, int w);
+
 // Record the calling thread's last error (swept_last_error) and return code.
 int set_error(int code, const std::string& msg);
 

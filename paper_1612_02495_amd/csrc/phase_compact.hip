@@ -1,0 +1,64 @@
+// Compacted wave engine for one periodic grid: one wave64 per tile as in the
+// register engine (phase_wave.hip), with each run of tiers laid out over the
+// part of the tile it touches (compact_tile.h).  Tiles, slots and phase
+// parities are those of the other engines, so all three can run alternate
+// phases of one run.
+#include "compact_tile.h"
+
+namespace swept {
+namespace {
+
+template <int KIND, typename T, int P, int ROLE>
+__global__ void __launch_bounds__(64)
+phase_compact_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, int hl, Consts<T> k) {
+  constexpr int S = Radius<KIND>::value;
+  constexpr int W = 64 * P;
+  constexpr int HALF = 32 * P;
+  constexpr int SLEN = W + 2 * S;
+  __shared__ T sb[compact::Lds<KIND, P>::band];
+  __shared__ T stg[compact::Lds<KIND, P>::stage];
+  const int64_t j = blockIdx.x;
+  const int64_t origin = j * (int64_t)W + (parity ? HALF : 0);
+  T* sL = parity ? slots + (nt + j) * SLEN : slots + j * SLEN;
+  T* sR = parity ? slots + ((j + 1) % nt) * SLEN : slots + (nt + j) * SLEN;
+  compact::tile_phase<KIND, T, P, ROLE>(u, n, origin, sL, sR, hv, hl, k, (int)threadIdx.x, sb, stg);
+}
+
+template <int KIND, typename T, int P>
+hipError_t launch_p(const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
+  auto kern = a.hv == 0 ? phase_compact_kernel<KIND, T, P, 0>
+              : (a.hl == 0 ? phase_compact_kernel<KIND, T, P, 2> : phase_compact_kernel<KIND, T, P, 1>);
+  hipLaunchKernelGGL(kern, dim3((unsigned)a.nt), dim3(64), 0, st, static_cast<T*>(a.u), static_cast<T*>(a.slots),
+                     a.n, a.nt, a.parity, a.hv, a.hl, k);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool compact_engine_supports(int kind, int w) {
+  if (w % 64 != 0) return false;
+  const int p = w / 64;
+  if (kind == kHeat) return p == 8 || p == 16;
+  return p == 8 || p == 16;
+}
+
+template <int KIND, typename T>
+hipError_t launch_phase_compact(const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
+  if (!compact_engine_supports(KIND, a.w)) return hipErrorInvalidValue;
+  switch (a.w / 64) {
+    case 8:
+      return launch_p<KIND, T, 8>(a, k, st);
+    case 16:
+      return launch_p<KIND, T, 16>(a, k, st);
+    default:
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_phase_compact<kHeat, float>(const PhaseArgs&, const Consts<float>&, hipStream_t);
+template hipError_t launch_phase_compact<kHeat, double>(const PhaseArgs&, const Consts<double>&, hipStream_t);
+template hipError_t launch_phase_compact<kKS, float>(const PhaseArgs&, const Consts<float>&, hipStream_t);
+template hipError_t launch_phase_compact<kKS, double>(const PhaseArgs&, const Consts<double>&, hipStream_t);
+
+}  // namespace swept

@@ -106,6 +106,7 @@ struct swept_plan_s {
   int h = 0;       // tiers per full phase
   int64_t nt = 0;  // tiles
   int engine = SWEPT_ENGINE_AUTO;
+  bool lds_fits = true;  // the LDS engine's tile fits the device's LDS
   int device = 0;
   void* slots = nullptr;
   size_t slots_bytes = 0;
@@ -119,15 +120,29 @@ namespace {
 
 size_t elem_size(int dtype) { return dtype == SWEPT_F64 ? sizeof(double) : sizeof(float); }
 
-bool use_wave(const swept_plan_s* p) {
-  if (p->engine == SWEPT_ENGINE_LDS) return false;
-  return swept::wave_engine_supports(p->kind, p->w);
+bool engine_supports(int engine, int kind, int w) {
+  if (engine == SWEPT_ENGINE_WAVE) return swept::wave_engine_supports(kind, w);
+  if (engine == SWEPT_ENGINE_COMPACT) return swept::compact_engine_supports(kind, w);
+  return true;
+}
+
+// The engine that runs the phases: the chosen one, or for AUTO the register
+// engine where it has a kernel and the LDS engine otherwise.
+int resolved_engine(const swept_plan_s* p) {
+  if (p->engine != SWEPT_ENGINE_AUTO) return p->engine;
+  return swept::wave_engine_supports(p->kind, p->w) ? SWEPT_ENGINE_WAVE : SWEPT_ENGINE_LDS;
 }
 
 template <int KIND, typename T>
 hipError_t launch_phase(const swept_plan_s* p, const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
-  if (use_wave(p)) return swept::launch_phase_wave<KIND, T>(a, k, st);
-  return swept::launch_phase_lds<KIND, T>(a, k, st);
+  switch (resolved_engine(p)) {
+    case SWEPT_ENGINE_WAVE:
+      return swept::launch_phase_wave<KIND, T>(a, k, st);
+    case SWEPT_ENGINE_COMPACT:
+      return swept::launch_phase_compact<KIND, T>(a, k, st);
+    default:
+      return swept::launch_phase_lds<KIND, T>(a, k, st);
+  }
 }
 
 template <typename T>
@@ -229,7 +244,7 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
     if (steps_per_cycle == 0 && swept::tune_lookup(kind, dtype, n, &te) && tile_ok(kind, te.tile_width, &why) &&
         n % te.tile_width == 0 && te.steps_per_cycle >= 0 &&
         te.steps_per_cycle * tiers_per_step(kind) <= full_tiers(kind, te.tile_width) &&
-        (te.engine != SWEPT_ENGINE_WAVE || swept::wave_engine_supports(kind, te.tile_width))) {
+        engine_supports(te.engine, kind, te.tile_width)) {
       w = te.tile_width;
       steps_per_cycle = te.steps_per_cycle;
       tuned_engine = te.engine;
@@ -309,17 +324,24 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
     return fail(SWEPT_ENOMEM, std::string("hipMalloc(naive buffer): ") + hipGetErrorString(e));
   }
   p->engine = tuned_engine;
-  if (lds > (size_t)max_lds) p->engine = SWEPT_ENGINE_WAVE;
+  p->lds_fits = lds <= (size_t)max_lds;
+  if (!p->lds_fits && (p->engine == SWEPT_ENGINE_LDS || p->engine == SWEPT_ENGINE_AUTO))
+    p->engine = SWEPT_ENGINE_WAVE;
   *out = p;
   return SWEPT_OK;
 }
 
 int swept_plan_set_engine(swept_plan p, int engine) {
   if (!p) return fail(SWEPT_EINVAL, "plan must not be NULL");
-  if (engine != SWEPT_ENGINE_AUTO && engine != SWEPT_ENGINE_LDS && engine != SWEPT_ENGINE_WAVE)
+  if (engine != SWEPT_ENGINE_AUTO && engine != SWEPT_ENGINE_LDS && engine != SWEPT_ENGINE_WAVE &&
+      engine != SWEPT_ENGINE_COMPACT)
     return fail(SWEPT_EINVAL, "unknown engine");
   if (engine == SWEPT_ENGINE_WAVE && !swept::wave_engine_supports(p->kind, p->w))
     return fail(SWEPT_EUNSUPPORTED, "no wave-resident kernel for this kind and tile width");
+  if (engine == SWEPT_ENGINE_COMPACT && !swept::compact_engine_supports(p->kind, p->w))
+    return fail(SWEPT_EUNSUPPORTED, "no compacted kernel for this kind and tile width");
+  if (engine == SWEPT_ENGINE_LDS && !p->lds_fits)
+    return fail(SWEPT_EUNSUPPORTED, "tile too wide for the LDS of this device");
   p->engine = engine;
   return SWEPT_OK;
 }
@@ -418,8 +440,8 @@ int swept_autotune(int64_t n, int kind, int dtype, double dt, double dx, double 
     if (n % w != 0 || n < w || !tile_ok(kind, w, &why)) continue;
     const int full_steps = full_tiers(kind, w) / tps;
     const int spcs[2] = {full_steps, full_steps / 2};
-    for (int eng : {SWEPT_ENGINE_WAVE, SWEPT_ENGINE_LDS}) {
-      if (eng == SWEPT_ENGINE_WAVE && !swept::wave_engine_supports(kind, w)) continue;
+    for (int eng : {SWEPT_ENGINE_COMPACT, SWEPT_ENGINE_WAVE, SWEPT_ENGINE_LDS}) {
+      if (!engine_supports(eng, kind, w)) continue;
       for (int si = 0; si < 2; ++si) {
         if (spcs[si] < 1 || (si == 1 && spcs[1] == spcs[0])) continue;
         cands.push_back({w, spcs[si], eng});

@@ -10,11 +10,12 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (SWEPT_ENGINE_AUTO, SWEPT_ENGINE_LDS, SWEPT_ENGINE_WAVE, SWEPT_F32, SWEPT_F64,
+from ._lib import (SWEPT_ENGINE_AUTO, SWEPT_ENGINE_COMPACT, SWEPT_ENGINE_LDS, SWEPT_ENGINE_WAVE, SWEPT_F32, SWEPT_F64,
                    SWEPT_HEAT_FTCS, SWEPT_KS_RK2, SweptError, check)
 
 KINDS = {"heat": SWEPT_HEAT_FTCS, "ks": SWEPT_KS_RK2}
-ENGINES = {"auto": SWEPT_ENGINE_AUTO, "lds": SWEPT_ENGINE_LDS, "wave": SWEPT_ENGINE_WAVE}
+ENGINES = {"auto": SWEPT_ENGINE_AUTO, "lds": SWEPT_ENGINE_LDS, "wave": SWEPT_ENGINE_WAVE,
+           "compact": SWEPT_ENGINE_COMPACT}
 
 
 def _kind(kind) -> int:
@@ -93,7 +94,7 @@ def swept_tile_geometry(kind, tile_width: int) -> dict:
     return {"full_tiers": t.value, "row_values": r.value, "edge_slot_values": e.value}
 
 
-ENGINE_NAMES = {SWEPT_ENGINE_AUTO: "auto", SWEPT_ENGINE_LDS: "lds", SWEPT_ENGINE_WAVE: "wave"}
+ENGINE_NAMES = {v: k for k, v in ENGINES.items()}
 
 
 def swept_autotune(n: int, kind, dtype, dt: float, dx: float, alpha: float = 0.0, steps: int = 0,
