@@ -166,11 +166,18 @@ def run_batch(args, wl):
     }
 
 
+CSRC = "paper_1612_02495_amd/csrc/"
+# Per engine: the sources that define its diamond kernel, and the committed
+# rocprofv3 counter summary for the heat FP64 N=2^20 w=1024 workload.
 KERNEL_SOURCES = {
-    "wave": ["paper_1612_02495_amd/csrc/phase_wave.hip", "paper_1612_02495_amd/csrc/stencil.h",
-             "paper_1612_02495_amd/csrc/internal.h"],
+    "wave": [CSRC + "phase_wave.hip", CSRC + "stencil.h", CSRC + "internal.h"],
+    "compact": [CSRC + "phase_compact.hip", CSRC + "compact_tile.h", CSRC + "wave_tile.h", CSRC + "stencil.h",
+                CSRC + "internal.h"],
 }
-TRAFFIC_SUMMARY = "profiles/phase_wave_heat_f64_n2p20_w1024_pmc.md"
+TRAFFIC_SUMMARY = {
+    "wave": "profiles/phase_wave_heat_f64_n2p20_w1024_pmc.md",
+    "compact": "profiles/phase_compact_heat_f64_n2p20_w1024_pmc.md",
+}
 
 
 def _traffic_from_profile(wl, tile, engine):
@@ -178,16 +185,20 @@ def _traffic_from_profile(wl, tile, engine):
     counter summary -- only if it covers this workload and the kernel source
     has not changed since the counters were taken; otherwise None."""
     import hashlib
-    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if engine == "auto":  # the library's AUTO choice for these widths
+        engine = "compact" if tile in (512, 1024) else "wave"
     if not (wl["kind"] == "heat" and wl["dtype"] == "f64" and wl["n"] == 2 ** 20 and tile == 1024
-            and engine in ("auto", "wave") and os.path.exists(path)):
+            and engine in TRAFFIC_SUMMARY):
+        return None
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY[engine])
+    if not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
         if ":" in line and not line.startswith(("#", "|", "`")):
             k, _, v = line.partition(":")
             fields[k.strip()] = v.strip()
-    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in KERNEL_SOURCES["wave"])
+    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in KERNEL_SOURCES[engine])
     if fields.get("source_sha256") != hashlib.sha256(src).hexdigest():
         return None
     try:

@@ -64,7 +64,8 @@ extern "C" {
 #define SWEPT_F64 1
 
 /* phase engines (swept_plan_set_engine) */
-#define SWEPT_ENGINE_AUTO 0 /* wave-resident engine where it applies, else LDS */
+#define SWEPT_ENGINE_AUTO 0 /* compacted engine where it applies, else the
+                               register engine, else LDS                      */
 #define SWEPT_ENGINE_LDS 1  /* tile in LDS, two tier rows, one thread block    */
 #define SWEPT_ENGINE_WAVE 2 /* tile in the registers of one wave64, DPP halos   */
 #define SWEPT_ENGINE_COMPACT 3 /* wave64 per tile, V/Lambda compacted onto the

@@ -126,10 +126,11 @@ bool engine_supports(int engine, int kind, int w) {
   return true;
 }
 
-// The engine that runs the phases: the chosen one, or for AUTO the register
-// engine where it has a kernel and the LDS engine otherwise.
+// The engine that runs the phases: the chosen one, or for AUTO the compacted
+// engine where it has a kernel, else the register engine, else LDS.
 int resolved_engine(const swept_plan_s* p) {
   if (p->engine != SWEPT_ENGINE_AUTO) return p->engine;
+  if (swept::compact_engine_supports(p->kind, p->w)) return SWEPT_ENGINE_COMPACT;
   return swept::wave_engine_supports(p->kind, p->w) ? SWEPT_ENGINE_WAVE : SWEPT_ENGINE_LDS;
 }
 
@@ -325,8 +326,9 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
   }
   p->engine = tuned_engine;
   p->lds_fits = lds <= (size_t)max_lds;
-  if (!p->lds_fits && (p->engine == SWEPT_ENGINE_LDS || p->engine == SWEPT_ENGINE_AUTO))
-    p->engine = SWEPT_ENGINE_WAVE;
+  // a tuned LDS choice that this device's LDS cannot hold falls back to AUTO
+  // (a register engine: the width check above guarantees one exists)
+  if (!p->lds_fits && p->engine == SWEPT_ENGINE_LDS) p->engine = SWEPT_ENGINE_AUTO;
   *out = p;
   return SWEPT_OK;
 }
