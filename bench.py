@@ -125,6 +125,8 @@ def run_batch(args, wl):
     n = np.array([p.n for p in probs])
     b = Batch(n, wl["kind"], wl["dtype"], [p.dt for p in probs], [p.dx for p in probs],
               [p.alpha for p in probs], T)
+    engine = "compact" if args.engine == "auto" else args.engine  # the batch's AUTO is the compacted engine
+    b.set_engine(engine)
     u = torch.tensor(np.concatenate([p.u0 for p in probs]), device="cuda")
     for _ in range(args.warmup):
         b.run(u)
@@ -156,7 +158,7 @@ def run_batch(args, wl):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": wl["dtype"],
         "data": "synthetic (seeded; see paper_1612_02495_amd/inputs.py)",
         "config": {"workload": wl["desc"], "grids": int(n.size), "total_points": int(n.sum()),
-                   "timesteps_per_run": T, "kind": wl["kind"], "persistent_grid": b.grid,
+                   "timesteps_per_run": T, "kind": wl["kind"], "engine": engine, "persistent_grid": b.grid,
                    "edge_slot_bytes": b.workspace_bytes, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": "batched persistent swept kernel (whole launch)",
                      "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",

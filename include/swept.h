@@ -245,6 +245,19 @@ int swept_batch_create(swept_batch* out, int32_t nprob, const int64_t* n, int ki
 int swept_batch_run(swept_batch b, void* u, int use_graph, void* stream);
 
 /*
+ * swept_batch_set_engine -- choose the per-tile algorithm of the persistent
+ * kernel: SWEPT_ENGINE_AUTO or SWEPT_ENGINE_COMPACT (compacted layouts, edge
+ * bands in LDS; the default) or SWEPT_ENGINE_WAVE (register engine, every
+ * tier over the whole tile).  Both give the same values bit for bit and leave
+ * the same edge slots.  Changing the engine re-sizes the persistent grid
+ * (the engines need different LDS) and drops a captured graph, so call it
+ * between runs, never while one is in flight.  SWEPT_ENGINE_LDS fails with
+ * EUNSUPPORTED, other values with EINVAL; on failure the plan keeps its
+ * engine.
+ */
+int swept_batch_set_engine(swept_batch b, int engine);
+
+/*
  * swept_batch_info -- total points, per-grid offsets into u (host array of
  * nprob entries, may be NULL), edge-slot bytes and persistent grid size.
  */

@@ -7,13 +7,15 @@ not load the library; the first call does.
 from .swept import (Plan, SweptError, naive_run, swept_last_error, swept_plan_create,
                     swept_plan_destroy, swept_plan_info, swept_plan_set_engine, swept_run,
                     swept_schedule, swept_tile_geometry, swept_autotune, swept_autotune_lookup,
-                    swept_autotune_forget, Batch, swept_batch_create, swept_batch_run, swept_batch_info,
+                    swept_autotune_forget, Batch, swept_batch_create, swept_batch_run, swept_batch_set_engine,
+                    swept_batch_info,
                     swept_batch_destroy, AdjointPlan, swept_heat, swept_adjoint_create, swept_forward_ckpt,
                     swept_adjoint_run, swept_adjoint_info, swept_adjoint_destroy)
 
 __all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
            "swept_plan_set_engine", "swept_plan_destroy", "swept_last_error", "swept_schedule",
            "swept_tile_geometry", "swept_autotune", "swept_autotune_lookup", "swept_autotune_forget",
-           "Batch", "swept_batch_create", "swept_batch_run", "swept_batch_info", "swept_batch_destroy",
+           "Batch", "swept_batch_create", "swept_batch_run", "swept_batch_set_engine", "swept_batch_info",
+           "swept_batch_destroy",
            "AdjointPlan", "swept_heat", "swept_adjoint_create", "swept_forward_ckpt", "swept_adjoint_run",
            "swept_adjoint_info", "swept_adjoint_destroy"]

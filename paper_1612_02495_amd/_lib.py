@@ -70,6 +70,7 @@ def _declare(lib):
     pl = ctypes.POINTER(i64)
     lib.swept_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, pl, i32, i32, pd, pd, pd, i64]
     lib.swept_batch_run.argtypes = [vp, vp, i32, vp]
+    lib.swept_batch_set_engine.argtypes = [vp, i32]
     lib.swept_batch_info.argtypes = [vp, pl, pl, ctypes.POINTER(sz), pi]
     lib.swept_batch_destroy.argtypes = [vp]
     lib.swept_batch_destroy.restype = None
@@ -80,7 +81,7 @@ def _declare(lib):
     lib.swept_adjoint_destroy.argtypes = [vp]
     lib.swept_adjoint_destroy.restype = None
     for name in ("swept_adjoint_create", "swept_forward_ckpt", "swept_adjoint_run", "swept_adjoint_info",
-                 "swept_batch_create", "swept_batch_run", "swept_batch_info", "swept_autotune", "swept_autotune_lookup", "swept_tile_geometry", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
+                 "swept_batch_create", "swept_batch_run", "swept_batch_set_engine", "swept_batch_info", "swept_autotune", "swept_autotune_lookup", "swept_tile_geometry", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
                  "swept_plan_set_engine", "swept_schedule"):
         getattr(lib, name).restype = i32
     return lib

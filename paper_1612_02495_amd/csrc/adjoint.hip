@@ -9,13 +9,13 @@
 // and operation order as the forward), dJ/du_0 = lambda_0, and
 // dJ/dalpha = (dt/dx^2) sum_m sum_i lambda_{m+1,i} (u_{m,i-1} + u_{m,i+1} - 2 u_{m,i}).
 //
-// Tiling.  Tiles of w = 64 points, one point per thread of a 64-thread block,
-// full (pure) phases of h = 32 steps; the T mod 32 leading steps run with the
+// Tiling.  Tiles of w = 64 points, one point per lane of one wave64, full
+// (pure) phases of h = 32 steps; the T mod 32 leading steps run with the
 // classic scheme and keep their states.  Forward: phase p writes its edge
 // slots out of place, into checkpoint p.  Reverse, for p = K .. 0, one fused
 // launch per phase: every tile
 //   1. recomputes its forward region (V then Lambda) from checkpoint p-1,
-//      keeping every tier in LDS;
+//      keeping every tier of its own point in the lane's registers;
 //   2. walks lambda down through the same region: its Lambda part first,
 //      taking the lambda values of later regions just outside each tier from
 //      lambda slots, then its V part, handing the two outermost values of each
@@ -32,6 +32,7 @@
 
 #include "internal.h"
 #include "swept.h"
+#include "wave_tile.h"
 
 namespace swept {
 namespace adj {
@@ -54,149 +55,195 @@ __global__ void consts_kernel(const double* __restrict__ alpha, int batch, doubl
   k[b] = c;
 }
 
-// Row of tile points computed at diamond tier d (V part d <= h, Lambda d > h).
+// Whether tile point x is computed at diamond tier d (V part d <= h, Lambda
+// d > h).
 __device__ __forceinline__ bool in_row(int x, int d) {
   if (d < kH) return x >= kA - d && x < kA + d;
-  if (d == kH) return x >= 0 && x < kW;
+  if (d == kH) return true;
   return x >= d - kH && x < kW - d + kH;
 }
 
-// MODE 0: forward phase writing checkpoint slots (or u_T); MODE 1: fused adjoint.
-template <int MODE>
+// Lane x inside [lo, lo + 2): the two points of an edge band.
+__device__ __forceinline__ bool in_pair(int x, int lo) { return (unsigned)(x - lo) < 2u; }
+
+// One swept region of one tile, held in one wave64: lane x owns tile point x
+// and keeps the region's states u(x, d) in registers, tier by tier; the
+// neighbours of a point come from DPP lane shifts and the edge bands enter
+// and leave through per-lane registers, so there is no LDS and no barrier.
+//
+// MODE 0: forward phase writing checkpoint slots (or u_T).  MODE 1: fused
+// adjoint (recompute, lambda walk, dJ/dalpha terms).  HV: the region has a V
+// part (every phase but the first); HL: it has a Lambda part (every phase
+// but the last).  Slots are position-major [p][t & 1] as in the forward
+// engines: consumer left input p = x + 1, right input p = x - a; producer
+// left side p = x (x <= a), right side p = x - a + 1 (x >= a - 1).
+template <int MODE, bool HV, bool HL>
 __global__ void __launch_bounds__(kW)
 region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const double* __restrict__ ck_in,
               double* __restrict__ ck_out, const double* __restrict__ gT, double* lam_slots, double* __restrict__ g_ur,
-              double* __restrict__ partial, const Consts<double>* __restrict__ kb, int64_t n, int64_t nt, int p,
-              int K) {
-  constexpr int NROW = MODE ? 2 * kH + 1 : 2;
-  __shared__ double hist[NROW][kW + 2];  // column x + 1, x in [-1, w]
-  __shared__ double sin_l[kSL], sin_r[kSL];
-  __shared__ double lam[2][kW + 2];
-  __shared__ double lin_l[kSL], lin_r[kSL];
-  __shared__ double red[kW];
-
+              double* __restrict__ partial, const Consts<double>* __restrict__ kb, int64_t n, int64_t nt, int p) {
+  using wave::dpp_move0;
+  using wave::kDppWaveShl1;
+  using wave::kDppWaveShr1;
+  using wave::pick;
+  constexpr int kDppWaveRor1 = 0x13C;  // lane i <- lane i-1, lane 0 <- lane 63
+  constexpr int kDppWaveRol1 = 0x134;  // lane i <- lane i+1, lane 63 <- lane 0
   const int x = threadIdx.x;
   const int64_t b = blockIdx.x / nt;
   const int64_t j = blockIdx.x % nt;
   const Consts<double> k = kb[b];
-  const int hv = p == 0 ? 0 : kH;
-  const int hl = p == K ? 0 : kH;
   const int par = p & 1;
   const int64_t origin = j * kW + (par ? kA : 0);
   const int64_t base = b * 2 * nt * kSL;
-  const int64_t sL = par ? (nt + j) * kSL : j * kSL;
-  const int64_t sR = par ? ((j + 1) % nt) * kSL : (nt + j) * kSL;
+  const int64_t sL = base + (par ? (nt + j) * kSL : j * kSL);
+  const int64_t sR = base + (par ? ((j + 1) % nt) * kSL : (nt + j) * kSL);
   int64_t gx = origin + x;
   if (gx >= n) gx -= n;
   const int64_t gidx = b * n + gx;
-#define ROW(d) (MODE ? (d) : ((d)&1))
 
   // ------------------------------------------------ forward recompute --
-  if (hv == 0) {
-    hist[ROW(kH)][x + 1] = ustart[gidx];
+  double hist[2 * kH];  // u(x, d), d = 0 .. 2h-1 (MODE 0 keeps only the live row)
+  double tipL = 0.0, tipR = 0.0;  // points -1 and w at tier h-1
+  if constexpr (!HV) {
+    hist[kH] = ustart[gidx];
   } else {
-    for (int i = x; i < kSL; i += kW) {
-      sin_l[i] = ck_in[base + sL + i];
-      sin_r[i] = ck_in[base + sR + i];
-    }
-    __syncthreads();
-    for (int d = 0; d <= kH; ++d) {
-      if (d > 0 && in_row(x, d))
-        hist[ROW(d)][x + 1] = heat_update(hist[ROW(d - 1)][x], hist[ROW(d - 1)][x + 1], hist[ROW(d - 1)][x + 2], k);
-      if (d < kH && x < 4) {
-        // edge bands of tier d: [a-d-2, a-d) from the left slot, [a+d, a+d+2) from the right
-        const int pos = x < 2 ? kA - d - 2 + x : kA + d + (x - 2);
-        hist[ROW(d)][pos + 1] = x < 2 ? sin_l[2 * (pos + 1) + (d & 1)] : sin_r[2 * (pos - kA) + (d & 1)];
+    // this lane's incoming band values, one per tier parity
+    const int64_t src = x < kA ? sL + 2 * (x + 1) : sR + 2 * (x - kA);
+    const double bv0 = ck_in[src], bv1 = ck_in[src + 1];
+    tipL = ck_in[sL + ((kH - 1) & 1)];
+    tipR = ck_in[sR + 2 * (kW - kA) + ((kH - 1) & 1)];
+    double row = 0.0;
+#pragma unroll
+    for (int t = 0; t < kH; ++t) {
+      // band of tier t: [a-t-2, a-t) and [a+t, a+t+2)
+      row = pick(in_pair(x, kA - t - 2) || in_pair(x, kA + t), (t & 1) ? bv1 : bv0, row);
+      hist[t] = row;
+      double lo = dpp_move0<kDppWaveShr1>(row), hi = dpp_move0<kDppWaveShl1>(row);
+      if (t == kH - 1) {
+        lo = pick(x == 0, tipL, lo);
+        hi = pick(x == kW - 1, tipR, hi);
       }
-      __syncthreads();
+      row = heat_update(lo, row, hi, k);
     }
+    hist[kH] = row;
   }
-  if (hl > 0) {
-    __syncthreads();
+  if constexpr (HL) {
+    double row = hist[kH];
+    double o0 = 0.0, o1 = 0.0;  // MODE 0: this lane's outgoing band values
+#pragma unroll
     for (int m = 0; m < kH; ++m) {
-      const int d = kH + m;
-      if (m > 0 && in_row(x, d))
-        hist[ROW(d)][x + 1] = heat_update(hist[ROW(d - 1)][x], hist[ROW(d - 1)][x + 1], hist[ROW(d - 1)][x + 2], k);
-      __syncthreads();
+      if (m > 0) {
+        const double lo = dpp_move0<kDppWaveShr1>(row), hi = dpp_move0<kDppWaveShl1>(row);
+        row = heat_update(lo, row, hi, k);
+        hist[kH + m] = row;
+      }
       if constexpr (MODE == 0) {
-        if (x < 4) {
-          const int pos = x < 2 ? m + x : kW - m - 2 + (x - 2);
-          const double v = hist[ROW(d)][pos + 1];
-          if (x < 2)
-            ck_out[base + sL + 2 * pos + (m & 1)] = v;
-          else
-            ck_out[base + sR + 2 * (pos - kA + 1) + (m & 1)] = v;
-        }
+        // band of Lambda tier m: [m, m+2) and [w-m-2, w-m)
+        const bool band = in_pair(x, m) || in_pair(x, kW - m - 2);
+        if (m & 1)
+          o1 = pick(band, row, o1);
+        else
+          o0 = pick(band, row, o0);
+      }
+    }
+    if constexpr (MODE == 0) {
+      // left side p = x at tiers m = x-1, x; right side p = x-a+1 at m = w-x-2, w-x-1
+      if (x <= kA) {
+        if (x <= kH - 1) ck_out[sL + 2 * x + (x & 1)] = (x & 1) ? o1 : o0;
+        if (x >= 1) ck_out[sL + 2 * x + ((x - 1) & 1)] = ((x - 1) & 1) ? o1 : o0;
+      }
+      if (x >= kA - 1) {
+        const int m0 = kW - x - 2, m1 = kW - x - 1;
+        if (m0 >= 0) ck_out[sR + 2 * (x - kA + 1) + (m0 & 1)] = (m0 & 1) ? o1 : o0;
+        if (m1 <= kH - 1) ck_out[sR + 2 * (x - kA + 1) + (m1 & 1)] = (m1 & 1) ? o1 : o0;
       }
     }
   } else if constexpr (MODE == 0) {
-    uT[gidx] = hist[ROW(kH)][x + 1];
+    uT[gidx] = hist[kH];
   }
-  if constexpr (MODE == 0) return;
-
-  // --------------------------------------------------- adjoint sweep --
-  __syncthreads();
-  for (int i = x; i < kSL; i += kW) {
-    lin_l[i] = lam_slots[base + sL + i];
-    lin_r[i] = lam_slots[base + sR + i];
-  }
-  __syncthreads();
-  // lambda values of later regions just outside Lambda tier t = h + m
-  auto incoming = [&](double* row, int t) {
-    const int m = t - kH;
-    if (x < 4) {
-      const int pos = x < 2 ? m - 2 + x : kW - m + (x - 2);
-      row[pos + 1] = x < 2 ? lin_l[2 * (pos + 1) + (m & 1)] : lin_r[2 * (pos - (kW - kH)) + (m & 1)];
+  if constexpr (MODE == 1) {
+    // --------------------------------------------------- adjoint sweep --
+    // lambda of later regions just outside Lambda tier h+m (m = 1 .. h):
+    // [m-2, m) from the left slot (p = pos + 1), [w-m, w-m+2) from the right
+    // (p = pos - (w - h)); one value per tier parity for every lane, and the
+    // two points beyond the tile ends at m = 1.
+    double in0 = 0.0, in1 = 0.0, ltipL = 0.0, ltipR = 0.0;
+    if constexpr (HL) {
+      const int64_t src = x < kW - kH ? sL + 2 * (x + 1) : sR + 2 * (x - (kW - kH));
+      in0 = lam_slots[src];
+      in1 = lam_slots[src + 1];
+      ltipL = lam_slots[sL + 1];
+      ltipR = lam_slots[sR + 2 * kH + 1];
     }
-  };
-  double acc = 0.0;
-  int cur = 0;
-  int d;
-  bool given;
-  if (hl == 0) {
-    lam[cur][x + 1] = gT[gidx];  // lambda_T
-    d = kH;
-    given = true;
-  } else {
-    incoming(lam[cur], 2 * kH);
-    d = 2 * kH - 1;
-    given = false;
-  }
-  __syncthreads();
-  const int dmin = hv > 0 ? 1 : kH;
-  for (; d >= dmin; --d) {
-    int at = cur;
-    if (!given) {
-      at = cur ^ 1;
-      if (in_row(x, d)) lam[at][x + 1] = heat_update(lam[cur][x], lam[cur][x + 1], lam[cur][x + 2], k);
-      __syncthreads();
+    double lam = 0.0, acc = 0.0;
+    double oL0 = 0.0, oL1 = 0.0, oR0 = 0.0, oR1 = 0.0;
+    if constexpr (HL)
+      lam = pick(in_pair(x, kH - 2) || in_pair(x, kW - kH), (kH & 1) ? in1 : in0, lam);
+    else
+      lam = gT[gidx];  // lambda at the region's top tier h
+#pragma unroll
+    for (int d = HL ? 2 * kH - 1 : kH; d >= (HV ? 1 : kH); --d) {
+      if (HL || d < kH) {  // lambda at tier d from tier d+1
+        double lo = dpp_move0<kDppWaveShr1>(lam), hi = dpp_move0<kDppWaveShl1>(lam);
+        if (HL && d == kH) {
+          lo = pick(x == 0, ltipL, lo);
+          hi = pick(x == kW - 1, ltipR, hi);
+        }
+        lam = heat_update(lo, lam, hi, k);
+      }
+      if (HV || d != kH) {  // dJ/dalpha term lambda(x,d) (L u)(x, d-1)
+        // Rotations rather than the shifts of the recompute: the shifted rows
+        // of the recompute are then not kept alive for this reuse, which
+        // would triple the registers the history needs.  The wrapped lanes
+        // (0 and w-1) are outside every row that reaches them, except at
+        // d = h where the triangle tips replace them.
+        const double um = hist[d - 1];
+        double ul = dpp_move0<kDppWaveRor1>(um), ur = dpp_move0<kDppWaveRol1>(um);
+        if (d == kH) {
+          ul = pick(x == 0, tipL, ul);
+          ur = pick(x == kW - 1, tipR, ur);
+        }
+        const double lap = (ul + ur) - 2.0 * um;
+        acc = pick(in_row(x, d), acc + lam * lap, acc);
+        // settle this tier's sum here so that no term waits in a register
+        asm volatile("" : "+v"(acc));
+      }
+      if (HV && d <= kH) {
+        // the two outermost values on each side of gap(d) go to the previous phase
+        const bool ol = in_pair(x, kA - d), orr = in_pair(x, kA + d - 2);
+        if (d & 1) {
+          oL1 = pick(ol, lam, oL1);
+          oR1 = pick(orr, lam, oR1);
+        } else {
+          oL0 = pick(ol, lam, oL0);
+          oR0 = pick(orr, lam, oR0);
+        }
+      }
+      if (!HV && d == kH) g_ur[gidx] = lam;
+      if (HL && d > kH) {
+        const int m = d - kH;
+        lam = pick(in_pair(x, m - 2) || in_pair(x, kW - m), (m & 1) ? in1 : in0, lam);
+      }
     }
-    given = false;
-    const bool computed = !(hv == 0 && d == kH);
-    if (computed && in_row(x, d)) {
-      const double* u = hist[d - 1];
-      const double lap = (u[x] + u[x + 2]) - 2.0 * u[x + 1];
-      acc += lam[at][x + 1] * lap;
+    if constexpr (HV) {
+      // left: lanes x <= a at d = a-x, a-x+1; right: lanes x >= a-1 at d = x-a+1, x-a+2 (d in [1, h])
+      if (x <= kA) {
+        const int d0 = kA - x, d1 = kA - x + 1;
+        if (d0 >= 1) lam_slots[sL + 2 * x + (d0 & 1)] = (d0 & 1) ? oL1 : oL0;
+        if (d1 <= kH) lam_slots[sL + 2 * x + (d1 & 1)] = (d1 & 1) ? oL1 : oL0;
+      }
+      if (x >= kA - 1) {
+        const int d0 = x - kA + 1, d1 = x - kA + 2;
+        if (d0 >= 1) lam_slots[sR + 2 * (x - kA + 1) + (d0 & 1)] = (d0 & 1) ? oR1 : oR0;
+        if (d1 <= kH) lam_slots[sR + 2 * (x - kA + 1) + (d1 & 1)] = (d1 & 1) ? oR1 : oR0;
+      }
     }
-    if (hv > 0 && d <= kH) {
-      // two outermost values on each side of gap(d) go to the previous phase
-      if (x == kA - d || x == kA - d + 1) lam_slots[base + sL + 2 * x + (d & 1)] = lam[at][x + 1];
-      if (x == kA + d - 2 || x == kA + d - 1) lam_slots[base + sR + 2 * (x - kA + 1) + (d & 1)] = lam[at][x + 1];
-    }
-    if (hv == 0 && d == kH) g_ur[gidx] = lam[at][x + 1];
-    if (d > kH && hl > 0) incoming(lam[at], d);
-    __syncthreads();
-    cur = at;
+    // per-tile sum in a fixed order (x += x + s, s = 32 .. 1), added to this
+    // tile's running sum
+#pragma unroll
+    for (int s = kW / 2; s > 0; s >>= 1) acc = acc + __shfl_down(acc, s, kW);
+    if (x == 0) partial[b * nt + j] += acc;
   }
-  // per-tile sum in a fixed order, added to this tile's running sum
-  red[x] = acc;
-  __syncthreads();
-  for (int s = kW / 2; s > 0; s >>= 1) {
-    if (x < s) red[x] += red[x + s];
-    __syncthreads();
-  }
-  if (x == 0) partial[b * nt + j] += red[0];
-#undef ROW
 }
 
 __global__ void __launch_bounds__(kRemThreads)
@@ -383,9 +430,10 @@ int swept_forward_ckpt(swept_adjoint a, const void* u0, const double* alpha, voi
     for (int p = 0; p <= a->K && e == hipSuccess; ++p) {
       const double* ck_in = p > 0 ? a->ckpt + (size_t)(p - 1) * pslots : nullptr;
       double* ck_out = p < a->K ? a->ckpt + (size_t)p * pslots : nullptr;
-      hipLaunchKernelGGL(swept::adj::region_kernel<0>, dim3((unsigned)(a->batch * a->nt)), dim3(kW), 0, st, ur,
-                         static_cast<double*>(uT), ck_in, ck_out, nullptr, nullptr, nullptr, nullptr, k, a->n, a->nt,
-                         p, a->K);
+      auto kern = p == 0 ? swept::adj::region_kernel<0, false, true>
+                  : (p == a->K ? swept::adj::region_kernel<0, true, false> : swept::adj::region_kernel<0, true, true>);
+      hipLaunchKernelGGL(kern, dim3((unsigned)(a->batch * a->nt)), dim3(kW), 0, st, ur, static_cast<double*>(uT), ck_in,
+                         ck_out, nullptr, nullptr, nullptr, nullptr, k, a->n, a->nt, p);
       e = hipGetLastError();
     }
   }
@@ -413,9 +461,10 @@ int swept_adjoint_run(swept_adjoint a, const void* g_uT, void* g_u0, double* g_a
     const double* ur = a->rem + (size_t)a->r * total;
     for (int p = a->K; p >= 0 && e == hipSuccess; --p) {
       const double* ck_in = p > 0 ? a->ckpt + (size_t)(p - 1) * pslots : nullptr;
-      hipLaunchKernelGGL(swept::adj::region_kernel<1>, dim3((unsigned)(a->batch * a->nt)), dim3(kW), 0, st, ur,
-                         nullptr, ck_in, nullptr, static_cast<const double*>(g_uT), a->lam_slots, lam_r, a->tiles, k,
-                         a->n, a->nt, p, a->K);
+      auto kern = p == 0 ? swept::adj::region_kernel<1, false, true>
+                  : (p == a->K ? swept::adj::region_kernel<1, true, false> : swept::adj::region_kernel<1, true, true>);
+      hipLaunchKernelGGL(kern, dim3((unsigned)(a->batch * a->nt)), dim3(kW), 0, st, ur, nullptr, ck_in, nullptr,
+                         static_cast<const double*>(g_uT), a->lam_slots, lam_r, a->tiles, k, a->n, a->nt, p);
       e = hipGetLastError();
     }
   }

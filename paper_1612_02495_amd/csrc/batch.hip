@@ -15,13 +15,16 @@
 // halves (2j, 2j+1), odd tile j is halves (2j+1, 2j+2 mod 2nt): the zig-zag of
 // Sec. 4.2 with uneven tiles.  The phase height is the pure-triangle height of
 // the smallest half, floor(c/2nt) P / s tiers (even for KS); larger halves
-// carry a flat top.  The per-tile algorithm is wave_tile.h.
+// carry a flat top.  The per-tile algorithm is either the register engine's
+// (wave_tile.h) or the compacted one (compact_tile.h, uneven-tile form, with
+// LDS band buffers and staging rows of its own for every wave).
 #include <algorithm>
 #include <cmath>
 #include <numeric>
 #include <string>
 #include <vector>
 
+#include "compact_tile.h"
 #include "internal.h"
 #include "swept.h"
 #include "wave_tile.h"
@@ -45,11 +48,16 @@ struct BatchItem {
 
 __global__ void batch_reset_kernel(int* queue) { *queue = 0; }
 
-template <int KIND, typename T, int P, int NW>
+// COMPACT: 0 register engine, 1 compacted engine.
+template <int KIND, typename T, int P, int NW, int COMPACT>
 __global__ void __launch_bounds__(64 * NW)
 batch_kernel(const BatchItem<T>* __restrict__ items, int nitems, T* u, T* slots, int64_t tiers, int* queue) {
   constexpr int S = Radius<KIND>::value;
   constexpr int SLEN = 64 * P + 2 * S;
+  constexpr int NB = COMPACT ? compact::Lds<KIND, P>::band : 1;
+  constexpr int NS = COMPACT ? compact::Lds<KIND, P>::stage : 1;
+  __shared__ T sbm[NW][NB];   // per wave: edge bands of the tile in hand
+  __shared__ T stgm[NW][NS];  // per wave: staging row for layout changes
   __shared__ int s_item;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -83,7 +91,11 @@ batch_kernel(const BatchItem<T>* __restrict__ items, int nitems, T* u, T* slots,
         g.kR = hb + (iR < hx ? 1 : 0);
         g.sL = parity ? slotB + (int64_t)j * SLEN : slotA + (int64_t)j * SLEN;
         g.sR = parity ? slotA + (int64_t)((j + 1) % pr.nt) * SLEN : slotB + (int64_t)j * SLEN;
-        wave::tile_phase<KIND, T, P, 3>(ring, pr.n, g, hv, hl, pr.k, lane);
+        if constexpr (COMPACT)
+          compact::tile_phase_g<KIND, T, P>(ring, pr.n, g.origin, g.sL, g.sR, g.kL, g.kR, hv, hl, pr.k, lane,
+                                            sbm[wave], stgm[wave]);
+        else
+          wave::tile_phase<KIND, T, P, 3>(ring, pr.n, g, hv, hl, pr.k, lane);
       }
       // the next phase's tiles read slots other waves of this group wrote
       __threadfence();
@@ -115,6 +127,7 @@ struct swept_batch_s {
   size_t slots_bytes = 0;
   int* queue = nullptr;
   int device = 0;
+  int engine = SWEPT_ENGINE_AUTO;  // AUTO runs the compacted engine
   int grid = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -124,15 +137,44 @@ struct swept_batch_s {
 
 namespace {
 
-template <int KIND, typename T>
+bool compact_engine(const swept_batch_s* b) { return b->engine != SWEPT_ENGINE_WAVE; }
+
+template <int KIND, typename T, int C>
 void* batch_kernel_ptr() {
-  return reinterpret_cast<void*>(swept::batch_kernel<KIND, T, swept::kBatchP, swept::kBatchNW>);
+  return reinterpret_cast<void*>(swept::batch_kernel<KIND, T, swept::kBatchP, swept::kBatchNW, C>);
 }
 
-void* kernel_for(int kind, int dtype) {
+template <int C>
+void* kernel_for_c(int kind, int dtype) {
   if (kind == SWEPT_HEAT_FTCS)
-    return dtype == SWEPT_F64 ? batch_kernel_ptr<swept::kHeat, double>() : batch_kernel_ptr<swept::kHeat, float>();
-  return dtype == SWEPT_F64 ? batch_kernel_ptr<swept::kKS, double>() : batch_kernel_ptr<swept::kKS, float>();
+    return dtype == SWEPT_F64 ? batch_kernel_ptr<swept::kHeat, double, C>() : batch_kernel_ptr<swept::kHeat, float, C>();
+  return dtype == SWEPT_F64 ? batch_kernel_ptr<swept::kKS, double, C>() : batch_kernel_ptr<swept::kKS, float, C>();
+}
+
+void* kernel_for(const swept_batch_s* b) {
+  return compact_engine(b) ? kernel_for_c<1>(b->kind, b->dtype) : kernel_for_c<0>(b->kind, b->dtype);
+}
+
+template <int KIND, typename T, int C>
+void launch_batch(const swept_batch_s* b, void* u, int64_t tiers, hipStream_t st) {
+  hipLaunchKernelGGL((swept::batch_kernel<KIND, T, swept::kBatchP, swept::kBatchNW, C>), dim3((unsigned)b->grid),
+                     dim3(64 * swept::kBatchNW), 0, st, static_cast<const BatchItem<T>*>(b->items), b->nprob,
+                     static_cast<T*>(u), static_cast<T*>(b->slots), tiers, b->queue);
+}
+
+template <int C>
+void launch_batch_c(const swept_batch_s* b, void* u, int64_t tiers, hipStream_t st) {
+  if (b->kind == SWEPT_HEAT_FTCS) {
+    if (b->dtype == SWEPT_F64)
+      launch_batch<swept::kHeat, double, C>(b, u, tiers, st);
+    else
+      launch_batch<swept::kHeat, float, C>(b, u, tiers, st);
+  } else {
+    if (b->dtype == SWEPT_F64)
+      launch_batch<swept::kKS, double, C>(b, u, tiers, st);
+    else
+      launch_batch<swept::kKS, float, C>(b, u, tiers, st);
+  }
 }
 
 hipError_t enqueue_batch(swept_batch_s* b, void* u, hipStream_t st) {
@@ -140,27 +182,30 @@ hipError_t enqueue_batch(swept_batch_s* b, void* u, hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tiers = b->steps * (b->kind == SWEPT_KS_RK2 ? 2 : 1);
-  const dim3 grid((unsigned)b->grid), block(64 * swept::kBatchNW);
-  if (b->kind == SWEPT_HEAT_FTCS) {
-    if (b->dtype == SWEPT_F64)
-      hipLaunchKernelGGL((swept::batch_kernel<swept::kHeat, double, swept::kBatchP, swept::kBatchNW>), grid, block,
-                         0, st, static_cast<const BatchItem<double>*>(b->items), b->nprob, static_cast<double*>(u),
-                         static_cast<double*>(b->slots), tiers, b->queue);
-    else
-      hipLaunchKernelGGL((swept::batch_kernel<swept::kHeat, float, swept::kBatchP, swept::kBatchNW>), grid, block,
-                         0, st, static_cast<const BatchItem<float>*>(b->items), b->nprob, static_cast<float*>(u),
-                         static_cast<float*>(b->slots), tiers, b->queue);
-  } else {
-    if (b->dtype == SWEPT_F64)
-      hipLaunchKernelGGL((swept::batch_kernel<swept::kKS, double, swept::kBatchP, swept::kBatchNW>), grid, block,
-                         0, st, static_cast<const BatchItem<double>*>(b->items), b->nprob, static_cast<double*>(u),
-                         static_cast<double*>(b->slots), tiers, b->queue);
-    else
-      hipLaunchKernelGGL((swept::batch_kernel<swept::kKS, float, swept::kBatchP, swept::kBatchNW>), grid, block, 0,
-                         st, static_cast<const BatchItem<float>*>(b->items), b->nprob, static_cast<float*>(u),
-                         static_cast<float*>(b->slots), tiers, b->queue);
-  }
+  if (compact_engine(b))
+    launch_batch_c<1>(b, u, tiers, st);
+  else
+    launch_batch_c<0>(b, u, tiers, st);
   return hipGetLastError();
+}
+
+// Persistent grid: as many workgroups as the device holds at once.
+hipError_t size_grid(swept_batch_s* b) {
+  int per_cu = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(b), 64 * swept::kBatchNW, 0);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  b->grid = (int)std::min<int64_t>((int64_t)per_cu * cus, b->nprob);
+  return hipSuccess;
+}
+
+void drop_graph(swept_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_u = nullptr;
 }
 
 template <typename T>
@@ -289,16 +334,34 @@ int swept_batch_create(swept_batch* out, int32_t nprob, const int64_t* n, int ki
     batch_free(b);
     return bhip(e, "hipMemcpy(batch items)");
   }
-  int per_cu = 0, cus = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(kind, dtype), 64 * swept::kBatchNW, 0);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+  e = size_grid(b);
   if (e != hipSuccess) {
     batch_free(b);
     return bhip(e, "occupancy query");
   }
-  if (per_cu < 1) per_cu = 1;
-  b->grid = (int)std::min<int64_t>((int64_t)per_cu * cus, nprob);
   *out = b;
+  return SWEPT_OK;
+}
+
+int swept_batch_set_engine(swept_batch b, int engine) {
+  if (!b) return bfail(SWEPT_EINVAL, "batch must not be NULL");
+  if (engine == SWEPT_ENGINE_LDS) return bfail(SWEPT_EUNSUPPORTED, "the batched kernel has no LDS engine");
+  if (engine != SWEPT_ENGINE_AUTO && engine != SWEPT_ENGINE_WAVE && engine != SWEPT_ENGINE_COMPACT)
+    return bfail(SWEPT_EINVAL, "unknown engine");
+  if (engine == b->engine) return SWEPT_OK;
+  int prev = -1;
+  hipError_t e = hipGetDevice(&prev);
+  if (e == hipSuccess && prev != b->device) e = hipSetDevice(b->device);
+  if (e != hipSuccess) return bhip(e, "hipSetDevice");
+  const int old = b->engine;
+  b->engine = engine;
+  e = size_grid(b);
+  if (prev != b->device) (void)hipSetDevice(prev);
+  if (e != hipSuccess) {
+    b->engine = old;
+    return bhip(e, "occupancy query");
+  }
+  drop_graph(b);
   return SWEPT_OK;
 }
 
@@ -316,12 +379,7 @@ int swept_batch_run(swept_batch b, void* u, int use_graph, void* stream) {
     e = enqueue_batch(b, u, st);
     if (e != hipSuccess) rc = bhip(e, "batch launch");
   } else {
-    if (b->exec && b->graph_u != u) {
-      (void)hipGraphExecDestroy(b->exec);
-      (void)hipGraphDestroy(b->graph);
-      b->exec = nullptr;
-      b->graph = nullptr;
-    }
+    if (b->exec && b->graph_u != u) drop_graph(b);
     if (!b->exec) {
       if (!b->cap_stream) e = hipStreamCreate(&b->cap_stream);
       if (e == hipSuccess) e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);

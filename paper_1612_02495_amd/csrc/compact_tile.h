@@ -91,13 +91,13 @@ __device__ __forceinline__ void v_run(T (&A)[R], T (&Q)[R], const T (&buf)[R][2]
 }
 
 // Lambda tiers of block b, counted from the base of the layout's own 64 R-
-// point tile: all B tiers (FULL) or those below t1.  Each collects the band
+// point tile: all B tiers (FULL) or those in [t0, t1).  Each collects the band
 // values of tier t ([S t, S t + 2S), lanes b and b+1; [64 R - S(t+2),
 // 64 R - S t), lanes 63-b and 62-b), then computes tier t+1 unless
 // t == tskip (the empty top of a full triangle; never inside a FULL block).
 template <int KIND, typename T, int R, bool FULL>
-__device__ __forceinline__ void l_blk(T (&A)[R], T (&Q)[R], T (&buf)[R][2], int b, int t1, int tskip, int lane,
-                                      const Consts<T>& k) {
+__device__ __forceinline__ void l_blk(T (&A)[R], T (&Q)[R], T (&buf)[R][2], int b, int t0, int t1, int tskip,
+                                      int lane, const Consts<T>& k) {
   constexpr int S = Radius<KIND>::value;
   constexpr int B = R / S;
   const bool mL0 = lane == b, mL1 = lane == b + 1;
@@ -106,7 +106,7 @@ __device__ __forceinline__ void l_blk(T (&A)[R], T (&Q)[R], T (&buf)[R][2], int 
 #pragma unroll
   for (int j = 0; j < B; ++j) {
     const int t = b * B + j;
-    if (FULL || t < t1) {
+    if (FULL || (t >= t0 && t < t1)) {
       T(&row)[R] = KIND == kHeat ? A : wave::row_of<T, R>(A, Q, j & 1);
 #pragma unroll
       for (int i = 0; i < 2 * S; ++i) {
@@ -123,15 +123,21 @@ __device__ __forceinline__ void l_blk(T (&A)[R], T (&Q)[R], T (&buf)[R][2], int 
   }
 }
 
-// Lambda tiers [0, t1) of a layout: whole blocks, then the guarded remainder.
+// Lambda tiers [t0, t1) of a layout: a guarded head block when t0 is not a
+// block boundary, whole blocks, then the guarded remainder.
 template <int KIND, typename T, int R>
-__device__ __forceinline__ void l_run(T (&A)[R], T (&Q)[R], T (&buf)[R][2], int t1, int tskip, int lane,
+__device__ __forceinline__ void l_run(T (&A)[R], T (&Q)[R], T (&buf)[R][2], int t0, int t1, int tskip, int lane,
                                       const Consts<T>& k) {
   constexpr int B = R / Radius<KIND>::value;
-  if (t1 <= 0) return;
+  if (t1 <= t0) return;
+  int b = t0 / B;
   const int bl = (t1 - 1) / B;
-  for (int b = 0; b < bl; ++b) l_blk<KIND, T, R, true>(A, Q, buf, b, t1, -1, lane, k);
-  l_blk<KIND, T, R, false>(A, Q, buf, bl, t1, tskip, lane, k);
+  if (t0 % B != 0 && b < bl) {
+    l_blk<KIND, T, R, false>(A, Q, buf, b, t0, t1, tskip, lane, k);
+    ++b;
+  }
+  for (; b < bl; ++b) l_blk<KIND, T, R, true>(A, Q, buf, b, t0, t1, -1, lane, k);
+  l_blk<KIND, T, R, false>(A, Q, buf, bl, t0, t1, tskip, lane, k);
 }
 
 // V layouts R, R + step, .., P - step.  `done` counts the V tiers already
@@ -190,7 +196,7 @@ __device__ __forceinline__ void l_narrow(T* sb, T* stg, int hl, bool empty_top, 
       }
       // entered at its first tier (done == kFirst): virtual tiers from 0
       const int tskip = empty_top ? hl - 1 - kFirst : -1;
-      l_run<KIND, T, R>(A, Q, buf, tend - kFirst, tskip, lane, k);
+      l_run<KIND, T, R>(A, Q, buf, 0, tend - kFirst, tskip, lane, k);
       done = tend;
       if (done >= hl && !empty_top) {
         // flat top of the trapezoid: the row at its top tier
@@ -311,7 +317,7 @@ __device__ __forceinline__ void tile_phase(T* u, int64_t n, int64_t origin, T* s
     constexpr int kNext = P > ST ? 32 * ST / S : 1 << 30;
     const int tend = hl < kNext ? hl : kNext;
     const int tskip = empty_top ? hl - 1 : -1;
-    l_run<KIND, T, P>(A, Q, buf, tend, tskip, lane, k);
+    l_run<KIND, T, P>(A, Q, buf, 0, tend, tskip, lane, k);
     int done = tend;
     if (done >= hl && !empty_top) {
 #pragma unroll
@@ -352,6 +358,241 @@ __device__ __forceinline__ void tile_phase(T* u, int64_t n, int64_t origin, T* s
           sR[i] = outR[it];
         }
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tiles with uneven halves (the batched kernel): kL and kR lanes of P points
+// left and right of the seam (1 .. 32 each), w = (kL + kR) P, seam a = kL P.
+// The V layouts are centred on the seam as above; the Lambda layouts on the
+// tile middle c = w / 2, starting with the narrowest layout that holds the
+// whole base (window [c - 32R, c + 32R) covering [0, w)), whose first tier is
+// then not a block boundary.  Layout points outside the tile are don't-care:
+// their LDS loads read zero and their stores are skipped.  The row passes
+// between the V and the Lambda part through the staging row.
+
+// Several waves of one workgroup run uneven tiles side by side, each with its
+// own LDS buffers and its own number of layout changes, so ordering inside a
+// tile is a wave-level matter: the LDS operations of one wave execute in
+// order, and a wavefront-scope fence keeps the compiler from moving LDS
+// accesses across a layout change.  (A workgroup barrier here could pair up
+// different layout changes of different waves.)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+struct GTile {
+  int w;  // tile points
+  int a;  // seam
+  int c;  // middle, w / 2
+};
+
+__device__ __forceinline__ bool in_tile(int x, int w) { return (unsigned)x < (unsigned)w; }
+
+template <int KIND, typename T>
+__device__ __forceinline__ T band_ld(const T* sb, int x, int q, int w) {
+  constexpr int S = Radius<KIND>::value;
+  return (x >= -S && x < w + S) ? sb[pad(2 * (x + S) + q)] : T(0);
+}
+
+template <int KIND, typename T, int P, int R>
+__device__ __forceinline__ void v_narrow_g(T* sb, T* stg, const GTile& g, int hv, int& done, int lane,
+                                           const Consts<T>& k) {
+  if constexpr (R < P) {
+    constexpr int S = Radius<KIND>::value;
+    constexpr int BN = (R + Step<KIND>::value) / S;
+    constexpr int kEnd = (32 * R / S - 1) / BN * BN;
+    const int tend = hv < kEnd ? hv : kEnd;
+    if (done < tend) {
+      const int xl = g.a - 32 * R + lane * R;
+      T A[R], Q[R], buf[R][2];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int x = xl + r;
+        A[r] = (done > 0 && in_tile(x, g.w)) ? stg[pad(x)] : T(0);
+        Q[r] = T(0);
+        buf[r][0] = band_ld<KIND>(sb, x, 0, g.w);
+        buf[r][1] = band_ld<KIND>(sb, x, 1, g.w);
+      }
+      const T tip0[S] = {};
+      v_run<KIND, T, R, false>(A, Q, buf, done, tend, lane, tip0, tip0, k);
+      done = tend;
+      wave_sync();
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (in_tile(xl + r, g.w)) stg[pad(xl + r)] = A[r];
+      wave_sync();
+    }
+    v_narrow_g<KIND, T, P, R + Step<KIND>::value>(sb, stg, g, hv, done, lane, k);
+  }
+}
+
+// Lambda layouts R, R - step, .., step (those not wider than the first one,
+// r0); the row arrives in stg.
+template <int KIND, typename T, int P, int R>
+__device__ __forceinline__ void l_narrow_g(T* sb, T* stg, const GTile& g, int r0, int hl, bool empty_top, int& done,
+                                           int lane, const Consts<T>& k) {
+  if constexpr (R > 0) {
+    constexpr int S = Radius<KIND>::value;
+    constexpr int ST = Step<KIND>::value;
+    if (R <= r0 && done < hl) {
+      const int first = (g.c - 32 * R) / S;  // tier where this layout's window starts the triangle
+      const int next = R > ST ? (g.c - 32 * (R - ST)) / S : (1 << 30);
+      const int tend = hl < next ? hl : next;
+      const int xl = g.c - 32 * R + lane * R;
+      T A[R], Q[R], buf[R][2];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int x = xl + r;
+        A[r] = in_tile(x, g.w) ? stg[pad(x)] : T(0);
+        Q[r] = T(0);
+        buf[r][0] = R == r0 ? T(0) : band_ld<KIND>(sb, x, 0, g.w);
+        buf[r][1] = R == r0 ? T(0) : band_ld<KIND>(sb, x, 1, g.w);
+      }
+      const int tskip = empty_top ? hl - 1 - first : -1;
+      l_run<KIND, T, R>(A, Q, buf, done - first, tend - first, tskip, lane, k);
+      done = tend;
+      if (done >= hl && !empty_top) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int x = xl + r;
+          if (x >= S * hl && x < g.w - S * hl) {
+            if (hl & 1)
+              buf[r][1] = A[r];
+            else
+              buf[r][0] = A[r];
+          }
+        }
+      }
+      wave_sync();
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int x = xl + r;
+        if (in_tile(x, g.w)) {
+          sb[pad(2 * (x + S))] = buf[r][0];
+          sb[pad(2 * (x + S) + 1)] = buf[r][1];
+          if (done < hl) stg[pad(x)] = A[r];
+        }
+      }
+      wave_sync();
+    }
+    l_narrow_g<KIND, T, P, R - ST>(sb, stg, g, r0, hl, empty_top, done, lane, k);
+  }
+}
+
+// One phase of one uneven tile: hv V tiers (0: read the row from u), then hl
+// Lambda tiers (0: write the row to u).  sL/sR are its edge slots (layout as
+// in wave_tile.h); sb and stg this wave's LDS band buffer and staging row.
+template <int KIND, typename T, int P>
+__device__ __forceinline__ void tile_phase_g(T* u, int64_t n, int64_t origin, T* sL, T* sR, int kL, int kR, int hv,
+                                             int hl, const Consts<T>& k, int lane, T* sb, T* stg) {
+  constexpr int S = Radius<KIND>::value;
+  constexpr int ST = Step<KIND>::value;
+  constexpr int NV = (2 * (32 * P + S) + 63) / 64;  // copy iterations per slot side
+  GTile g;
+  g.w = (kL + kR) * P;
+  g.a = kL * P;
+  g.c = g.w / 2;
+  const int nL = 2 * (g.a + S), nR = 2 * (g.w - g.a + S);  // slot values read or written per side
+
+  if (hv == 0) {
+    T in[P];
+#pragma unroll
+    for (int it = 0; it < P; ++it) {
+      const int x = it * 64 + lane;
+      int64_t g2 = origin + x;
+      if (g2 >= n) g2 -= n;
+      in[it] = x < g.w ? u[g2] : T(0);
+    }
+#pragma unroll
+    for (int it = 0; it < P; ++it) {
+      const int x = it * 64 + lane;
+      if (x < g.w) stg[pad(x)] = in[it];
+    }
+    wave_sync();
+  } else {
+    {
+      T inL[NV], inR[NV];
+#pragma unroll
+      for (int it = 0; it < NV; ++it) {
+        const int i = it * 64 + lane;
+        inL[it] = i < nL ? sL[i] : T(0);
+        inR[it] = i < nR ? sR[i] : T(0);
+      }
+#pragma unroll
+      for (int it = 0; it < NV; ++it) {
+        const int i = it * 64 + lane;
+        if (i < nL) sb[pad(i)] = inL[it];
+        if (i < nR) sb[pad(nL + i)] = inR[it];
+      }
+    }
+    wave_sync();
+    int done = 0;
+    v_narrow_g<KIND, T, P, ST>(sb, stg, g, hv, done, lane, k);
+    const int xl = g.a - 32 * P + lane * P;
+    T A[P], Q[P], buf[P][2];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      const int x = xl + r;
+      A[r] = (done > 0 && in_tile(x, g.w)) ? stg[pad(x)] : T(0);
+      Q[r] = T(0);
+      buf[r][0] = band_ld<KIND>(sb, x, 0, g.w);
+      buf[r][1] = band_ld<KIND>(sb, x, 1, g.w);
+    }
+    T tipL[S], tipR[S];
+    const int tp = (hv - 1) & 1;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      tipL[i] = sb[pad(2 * i + tp)];
+      tipR[i] = sb[pad(2 * (g.w + S + i) + tp)];
+    }
+    v_run<KIND, T, P, true>(A, Q, buf, done, hv, lane, tipL, tipR, k);
+    // flat tops of the producer trapezoids: tile points outside the gap
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      const int x = xl + r;
+      if (x < g.a - S * hv || x >= g.a + S * hv) A[r] = wave::pick((hv & 1) != 0, buf[r][1], buf[r][0]);
+    }
+    wave_sync();  // the V's reads of sb and stg precede the writes below
+    if (hl == 0) {
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        const int x = xl + r;
+        if (in_tile(x, g.w)) {
+          int64_t g2 = origin + x;
+          if (g2 >= n) g2 -= n;
+          u[g2] = A[r];
+        }
+      }
+      return;
+    }
+#pragma unroll
+    for (int r = 0; r < P; ++r)
+      if (in_tile(xl + r, g.w)) stg[pad(xl + r)] = A[r];
+    wave_sync();
+  }
+  // narrowest layout whose window holds the whole base: 32 r0 >= c
+  const int r0 = ((g.c + 32 * ST - 1) / (32 * ST)) * ST;
+  const bool empty_top = 2 * S * hl >= g.w;
+  int done = 0;
+  l_narrow_g<KIND, T, P, P>(sb, stg, g, r0, hl, empty_top, done, lane, k);
+  // outgoing slots: producer left side p = x (x < a + S), right side
+  // p = x - a + S (x >= a - S)
+  {
+    T oL[NV], oR[NV];
+#pragma unroll
+    for (int it = 0; it < NV; ++it) {
+      const int i = it * 64 + lane;
+      oL[it] = i < nL ? sb[pad(2 * S + i)] : T(0);
+      oR[it] = i < nR ? sb[pad(2 * g.a + i)] : T(0);
+    }
+#pragma unroll
+    for (int it = 0; it < NV; ++it) {
+      const int i = it * 64 + lane;
+      if (i < nL) sL[i] = oL[it];
+      if (i < nR) sR[i] = oR[it];
     }
   }
 }

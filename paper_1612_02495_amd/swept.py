@@ -152,6 +152,11 @@ def swept_batch_run(batch, u, use_graph: bool = True, stream=None) -> None:
                                      _stream_ptr(u, stream)))
 
 
+def swept_batch_set_engine(batch, engine) -> None:
+    e = ENGINES[engine] if isinstance(engine, str) else int(engine)
+    check(_lib.lib().swept_batch_set_engine(batch, e))
+
+
 def swept_batch_info(batch, nprob: int) -> dict:
     tot, ws, grid = ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_int()
     offs = np.zeros(nprob, dtype=np.int64)
@@ -180,6 +185,12 @@ class Batch:
         self.total_points = inf["total_points"]
         self.grid = inf["grid"]
         self.workspace_bytes = inf["workspace_bytes"]
+
+    def set_engine(self, engine):
+        """'auto' / 'compact' (compacted layouts) or 'wave' (register engine)."""
+        swept_batch_set_engine(self._h, engine)
+        self.grid = swept_batch_info(self._h, self.n.size)["grid"]
+        return self
 
     def run(self, u, use_graph: bool = True, stream=None):
         if not u.is_cuda or u.dtype != self.dtype or u.numel() != self.total_points or not u.is_contiguous():
@@ -368,6 +379,7 @@ class Plan:
 __all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
            "swept_plan_set_engine", "swept_plan_destroy", "swept_last_error", "swept_schedule",
            "swept_tile_geometry", "swept_autotune", "swept_autotune_lookup", "swept_autotune_forget",
-           "Batch", "swept_batch_create", "swept_batch_run", "swept_batch_info", "swept_batch_destroy",
+           "Batch", "swept_batch_create", "swept_batch_run", "swept_batch_set_engine", "swept_batch_info",
+           "swept_batch_destroy",
            "AdjointPlan", "swept_heat", "swept_adjoint_create", "swept_forward_ckpt", "swept_adjoint_run",
            "swept_adjoint_info", "swept_adjoint_destroy"]

@@ -1,5 +1,6 @@
 """Batched persistent kernel on the GPU: every grid of the batch equals its
-own naive run (and the oracle) bit for bit; graph replays equal eager runs."""
+own naive run (and the oracle) bit for bit with either per-tile engine
+(compacted layouts or register engine); graph replays equal eager runs."""
 import numpy as np
 import pytest
 
@@ -33,11 +34,13 @@ def _batch_case(kind, dtype, steps, seed=0, m=40):
     return n, dt, dx, alpha, u0
 
 
+@pytest.mark.parametrize("engine", ["compact", "wave"])
 @pytest.mark.parametrize("kind,dtype,steps", [("heat", torch.float64, 300), ("heat", torch.float32, 129),
-                                              ("ks", torch.float64, 61)])
-def test_batch_equals_per_grid_naive_and_oracle(kind, dtype, steps):
+                                              ("ks", torch.float64, 61), ("ks", torch.float32, 40)])
+def test_batch_equals_per_grid_naive_and_oracle(kind, dtype, steps, engine):
+    print(f"batch {engine} {kind} {dtype} steps={steps}", flush=True)
     n, dt, dx, alpha, u0 = _batch_case(kind, dtype, steps)
-    b = Batch(n, kind, dtype, dt, dx, alpha, steps)
+    b = Batch(n, kind, dtype, dt, dx, alpha, steps).set_engine(engine)
     u = torch.tensor(np.concatenate(u0), dtype=dtype, device="cuda")
     b.run(u, use_graph=True)
     torch.cuda.synchronize()
@@ -55,9 +58,10 @@ def test_batch_equals_per_grid_naive_and_oracle(kind, dtype, steps):
             assert np.array_equal(parts[i], ref), f"grid {i} (n={n[i]}) differs from the oracle"
 
 
-def test_batch_graph_replays_match_eager():
+@pytest.mark.parametrize("engine", ["compact", "wave"])
+def test_batch_graph_replays_match_eager(engine):
     n, dt, dx, alpha, u0 = _batch_case("heat", torch.float64, 200, seed=5, m=24)
-    b = Batch(n, "heat", torch.float64, dt, dx, alpha, 200)
+    b = Batch(n, "heat", torch.float64, dt, dx, alpha, 200).set_engine(engine)
     state = torch.tensor(np.concatenate(u0), dtype=torch.float64, device="cuda")
     g = torch.empty_like(state)
     e = torch.empty_like(state)
@@ -97,3 +101,20 @@ def test_batch_full_workload_sampled():
         plan.naive(v, 5000)
         torch.cuda.synchronize()
         assert np.array_equal(parts[i], v.cpu().numpy()), f"grid {i} (n={n[i]})"
+
+
+def test_batch_engines_agree_and_switch():
+    n, dt, dx, alpha, u0 = _batch_case("ks", torch.float64, 33, seed=9, m=20)
+    b = Batch(n, "ks", torch.float64, dt, dx, alpha, 33)
+    x = torch.tensor(np.concatenate(u0), device="cuda")
+    y = x.clone()
+    b.run(x)                      # default: compacted, graph
+    b.set_engine("wave").run(y)   # register engine: the graph is re-captured
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+    b.set_engine("compact").run(y, use_graph=False)
+    b.run(x, use_graph=False)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+    with pytest.raises(Exception):
+        b.set_engine("lds")
