@@ -48,10 +48,13 @@ def _load():
         pf = ctypes.POINTER(ctypes.c_float)
         lib.oracle_heat_f64.argtypes = [pd, i64, dbl, dbl, dbl, i64]
         lib.oracle_heat_f32.argtypes = [pf, i64, dbl, dbl, dbl, i64]
+        lib.oracle_heat_insulated_f64.argtypes = [pd, i64, dbl, dbl, dbl, i64]
+        lib.oracle_heat_insulated_f32.argtypes = [pf, i64, dbl, dbl, dbl, i64]
         lib.oracle_ks_f64.argtypes = [pd, i64, dbl, dbl, i64]
         lib.oracle_ks_f32.argtypes = [pf, i64, dbl, dbl, i64]
         lib.oracle_heat_adjoint_f64.argtypes = [pd, pd, i64, dbl, dbl, dbl, i64, i64, pd, pd, pd]
-        for f in (lib.oracle_heat_f64, lib.oracle_heat_f32, lib.oracle_ks_f64, lib.oracle_ks_f32,
+        for f in (lib.oracle_heat_f64, lib.oracle_heat_f32, lib.oracle_heat_insulated_f64,
+                  lib.oracle_heat_insulated_f32, lib.oracle_ks_f64, lib.oracle_ks_f32,
                   lib.oracle_heat_adjoint_f64):
             f.restype = ctypes.c_int
         _lib = lib
@@ -81,6 +84,16 @@ def heat(u0, alpha: float, dt: float, dx: float, steps: int, dtype=np.float64) -
     a = _arr(u0, dtype)
     f = lib.oracle_heat_f64 if a.dtype == np.float64 else lib.oracle_heat_f32
     _check(f(_ptr(a), a.size, float(alpha), float(dt), float(dx), int(steps)), "oracle_heat")
+    return a
+
+
+def heat_insulated(u0, alpha: float, dt: float, dx: float, steps: int, dtype=np.float64) -> np.ndarray:
+    """Heat FTCS on a rod with insulated ends (Sec. 4.1): mirror ghosts about
+    the end nodes, u[-1] = u[1] and u[n] = u[n-2]; `steps` full timesteps."""
+    lib = _load()
+    a = _arr(u0, dtype)
+    f = lib.oracle_heat_insulated_f64 if a.dtype == np.float64 else lib.oracle_heat_insulated_f32
+    _check(f(_ptr(a), a.size, float(alpha), float(dt), float(dx), int(steps)), "oracle_heat_insulated")
     return a
 
 

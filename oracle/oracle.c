@@ -113,6 +113,66 @@ int oracle_heat_f32(float* u, int64_t n, double alpha, double dt, double dx, int
     return ORACLE_OK;
 }
 
+/* ----------------------------------------------- heat, insulated rod -- */
+/*
+ * The rod with insulated ends of Sec. 4.1 (Appendix, "insulated boundary
+ * conditions at both ends"): n nodes, the same interior update, and mirror
+ * ghosts about the end nodes, u_{-1} = u_1 and u_n = u_{n-2}.  The printed
+ * ghost relations are garbled; the right-hand one (ghost n+1 equals node n-1
+ * in 1-based numbering) is a mirror about the end node, and the left-hand one
+ * is read the same way.  n >= 2.
+ */
+static void heat_ins_step_f64(const double* u, double* v, int64_t n, double fo, double c) {
+    for (int64_t i = 0; i < n; ++i) {
+        double left = i == 0 ? u[1] : u[i - 1];
+        double right = i == n - 1 ? u[n - 2] : u[i + 1];
+        v[i] = fo * (right + left) + c * u[i];
+    }
+}
+
+static void heat_ins_step_f32(const float* u, float* v, int64_t n, float fo, float c) {
+    for (int64_t i = 0; i < n; ++i) {
+        float left = i == 0 ? u[1] : u[i - 1];
+        float right = i == n - 1 ? u[n - 2] : u[i + 1];
+        v[i] = fo * (right + left) + c * u[i];
+    }
+}
+
+int oracle_heat_insulated_f64(double* u, int64_t n, double alpha, double dt, double dx, int64_t steps) {
+    if (!u || n < 2 || steps < 0) return ORACLE_EINVAL;
+    double fo = (alpha * dt) / (dx * dx);
+    double c = 1.0 - 2.0 * fo;
+    double* v = (double*)malloc((size_t)n * sizeof(double));
+    if (!v) return ORACLE_ENOMEM;
+    double* cur = u;
+    double* nxt = v;
+    for (int64_t m = 0; m < steps; ++m) {
+        heat_ins_step_f64(cur, nxt, n, fo, c);
+        double* t = cur; cur = nxt; nxt = t;
+    }
+    if (cur != u) memcpy(u, cur, (size_t)n * sizeof(double));
+    free(v);
+    return ORACLE_OK;
+}
+
+int oracle_heat_insulated_f32(float* u, int64_t n, double alpha, double dt, double dx, int64_t steps) {
+    if (!u || n < 2 || steps < 0) return ORACLE_EINVAL;
+    double fo_d = (alpha * dt) / (dx * dx);
+    float fo = (float)fo_d;
+    float c = (float)(1.0 - 2.0 * fo_d);
+    float* v = (float*)malloc((size_t)n * sizeof(float));
+    if (!v) return ORACLE_ENOMEM;
+    float* cur = u;
+    float* nxt = v;
+    for (int64_t m = 0; m < steps; ++m) {
+        heat_ins_step_f32(cur, nxt, n, fo, c);
+        float* t = cur; cur = nxt; nxt = t;
+    }
+    if (cur != u) memcpy(u, cur, (size_t)n * sizeof(float));
+    free(v);
+    return ORACLE_OK;
+}
+
 /* ------------------------------------------------------------------ KS -- */
 
 typedef struct { double i4dx, idx2, idx4, dt, dth; } ks_consts;

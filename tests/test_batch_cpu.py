@@ -40,6 +40,7 @@ def test_batch_null_handles():
     lib = _lib.lib()
     assert lib.swept_batch_run(None, None, 1, None) == _lib.SWEPT_EINVAL
     assert lib.swept_batch_info(None, None, None, None, None) == _lib.SWEPT_EINVAL
+    assert lib.swept_batch_set_engine(None, _lib.SWEPT_ENGINE_COMPACT) == _lib.SWEPT_EINVAL
     lib.swept_batch_destroy(None)
     h = ctypes.c_void_p()
     assert lib.swept_batch_create(ctypes.byref(h), 0, None, 0, 1, None, None, None, 1) == _lib.SWEPT_EINVAL
