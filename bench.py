@@ -9,7 +9,8 @@ Prints one JSON line with the swept throughput (`value`), the naive kernel's
 throughput on the same workload, the roofline of the dominant kernel (the
 diamond phase) and the CPU oracle's throughput on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload heat|heat_f32|ks]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload heat|heat_f32|heat_rod|ks|batch|batch_ks|adjoint]
 """
 from __future__ import annotations
 
@@ -30,8 +31,8 @@ METRIC = "cell-updates/sec, swept vs naive on 1 GPU (FP64 heat/KS); adjoint grad
 # in stencil.h; negation is a free source modifier):
 #   heat: Fo*(r + l) + c*o                        -> 4
 #   KS:   rhs 18 + (u + h*rhs) 2, per sub-step    -> 20  (two sub-steps per step)
-FLOPS_PER_TIER_UPDATE = {"heat": 4, "ks": 20}
-TIERS_PER_STEP = {"heat": 1, "ks": 2}
+FLOPS_PER_TIER_UPDATE = {"heat": 4, "heat_insulated": 4, "ks": 20}
+TIERS_PER_STEP = {"heat": 1, "heat_insulated": 1, "ks": 2}
 # Plain-ALU peak for add/mul-only code (no FMA: the bit-exact operation order
 # has none; packed FP32 is disabled): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -41,6 +42,9 @@ WORKLOADS = {
                  desc="heat FTCS periodic, N=2^20, FP64, Fo=1/4, 8-mode u0, 1e5 steps per run"),
     "heat_f32": dict(kind="heat", dtype="f32", n=2 ** 20, horizon=100000, tile=0,
                      desc="heat FTCS periodic, N=2^20, FP32, Fo=1/4, 8-mode u0, 1e5 steps per run"),
+    "heat_rod": dict(kind="heat_insulated", dtype="f64", n=2 ** 20, horizon=100000, tile=0,
+                     desc="heat FTCS on a rod with insulated ends (Sec. 4.1), N=2^20 nodes, FP64, Fo=1/4, "
+                          "temperature gradient plus 8 cosine modes, 1e5 steps per run"),
     "ks": dict(kind="ks", dtype="f64", n=2 ** 20, horizon=20000, tile=0,
                desc="Kuramoto-Sivashinsky RK2 periodic, N=2^20, FP64, dx=0.5, dt=0.005, 2e4 steps per run"),
     "batch": dict(kind="heat", dtype="f64", n=0, horizon=5000, tile=0, batch=4096,
@@ -213,6 +217,8 @@ def _problem(wl):
     from paper_1612_02495_amd import inputs
     if wl["kind"] == "heat":
         return inputs.heat_large(n=wl["n"], steps=wl["horizon"])
+    if wl["kind"] == "heat_insulated":
+        return inputs.heat_rod(n=wl["n"], steps=wl["horizon"])
     return inputs.ks(n=wl["n"], steps=wl["horizon"])
 
 
@@ -238,6 +244,9 @@ def cpu_baseline(wl, budget_steps):
     if wl["kind"] == "heat":
         oracle.heat(p.u0, p.alpha, p.dt, p.dx, budget_steps,
                     dtype=np.float64 if wl["dtype"] == "f64" else np.float32)
+    elif wl["kind"] == "heat_insulated":
+        oracle.heat_insulated(p.u0, p.alpha, p.dt, p.dx, budget_steps,
+                              dtype=np.float64 if wl["dtype"] == "f64" else np.float32)
     else:
         oracle.ks(p.u0, p.dt, p.dx, budget_steps, dtype=np.float64 if wl["dtype"] == "f64" else np.float32)
     el = time.perf_counter() - t0
@@ -343,7 +352,7 @@ def main(argv=None):
         v = torch.tensor(p.u0, dtype=tdtype, device="cuda")
         plan.naive(v, min(T, 100))
         t_naive = _time_runs(lambda: plan.naive(v, T), k_naive, torch)
-        bytes_per_update = (16 if wl["kind"] == "heat" else 40) // (1 if wl["dtype"] == "f64" else 2)
+        bytes_per_update = (40 if wl["kind"] == "ks" else 16) // (1 if wl["dtype"] == "f64" else 2)
         naive = {"value": p.n * T * k_naive / t_naive, "ms_per_step": 1e3 * t_naive / k_naive,
                  "ms_per_timestep": 1e3 * t_naive / (k_naive * T),
                  "hbm_bound": {"bytes_per_cell_update": bytes_per_update,
@@ -352,7 +361,7 @@ def main(argv=None):
 
     cpu = None
     if not args.no_cpu_baseline:
-        budget = args.cpu_steps or (4000 if wl["kind"] == "heat" else 300)
+        budget = args.cpu_steps or (300 if wl["kind"] == "ks" else 4000)
         cpu = cpu_baseline(wl, budget)
 
     out = {

@@ -15,12 +15,18 @@
  * every entry point below returns exactly what the plain timestepper returns
  * for the same precision and operation order.
  *
- * Schemes (Sec. 4.1 and Appendix; periodic boundaries, index (i+k) mod n):
+ * Schemes (Sec. 4.1 and Appendix; periodic boundaries, index (i+k) mod n,
+ * except for the insulated rod):
  *   SWEPT_HEAT_FTCS  T_i^{m+1} = Fo (T_{i+1}^m + T_{i-1}^m) + (1 - 2 Fo) T_i^m,
  *                    Fo = alpha dt / dx^2                       (Eq. HeatDisc)
  *   SWEPT_KS_RK2     Kuramoto-Sivashinsky, 5-point central differences
  *                    (Eq. KSDisc) advanced by the RK2 midpoint rule
  *                    (predictor with dt/2, then final with dt).
+ *   SWEPT_HEAT_INSULATED  the heat scheme on a rod of n nodes with insulated
+ *                    ends (Sec. 4.1; Appendix): mirror ghosts about the end
+ *                    nodes, T_{-1} = T_1 and T_n = T_{n-2}.  The rod is laid
+ *                    on the same ring of tiles; only the tiles that hold node
+ *                    0 or n-1 (where the ring closes) use the ghost values.
  *
  * Conventions shared by all entry points
  *   - Return value: SWEPT_OK (0) or a negative swept status code.  Nothing
@@ -58,6 +64,10 @@ extern "C" {
 /* stencil kinds */
 #define SWEPT_HEAT_FTCS 0
 #define SWEPT_KS_RK2 1
+#define SWEPT_HEAT_INSULATED 2 /* heat, rod with insulated ends: plans with
+                                  tile_width 512 or 1024 (n a multiple of
+                                  it), swept on the compacted engine; not in
+                                  the batched or adjoint entry points       */
 
 /* element types */
 #define SWEPT_F32 0
@@ -78,9 +88,10 @@ typedef struct swept_plan_s* swept_plan;
  * swept_plan_create -- build a plan for one periodic grid of n points.
  *   out             receives the plan handle (host pointer, required).
  *   n               number of grid points, >= tile width, multiple of it.
- *   kind, dtype     SWEPT_HEAT_FTCS / SWEPT_KS_RK2, SWEPT_F32 / SWEPT_F64.
+ *   kind, dtype     SWEPT_HEAT_FTCS / SWEPT_KS_RK2 / SWEPT_HEAT_INSULATED,
+ *                   SWEPT_F32 / SWEPT_F64.
  *   dt, dx          timestep and grid spacing (finite, dx != 0).
- *   alpha           diffusivity (heat only; ignored for KS).
+ *   alpha           diffusivity (heat kinds only; ignored for KS).
  *   tile_width      points per tile ("node", Sec. 4.2): a multiple of 2s
  *                   (s = 1 heat, 2 KS) and of 8 for KS, 4..4096; 0 picks one:
  *                   the autotuned configuration for (kind, dtype, n) when

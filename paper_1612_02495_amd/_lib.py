@@ -20,6 +20,7 @@ SWEPT_ENOMEM = -3
 SWEPT_EDEVICE = -4
 
 SWEPT_HEAT_FTCS = 0
+SWEPT_HEAT_INSULATED = 2
 SWEPT_KS_RK2 = 1
 SWEPT_F32 = 0
 SWEPT_F64 = 1

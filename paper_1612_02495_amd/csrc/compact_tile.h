@@ -49,10 +49,11 @@ struct Lds {
 // 32: all B tiers (FULL) or those below t1.  Left band of tier t:
 // [-S(t+2), -S t) from the seam, lanes 31-b and 30-b; right band
 // [S t, S(t+2)), lanes 32+b and 33+b.
-template <int KIND, typename T, int R, bool FULL, bool TIPS>
+template <int KIND, typename T, int R, bool FULL, bool TIPS, bool INS = false>
 __device__ __forceinline__ void v_blk(T (&A)[R], T (&Q)[R], const T (&buf)[R][2], int b, int t1, int lane,
                                       const T (&tipL)[Radius<KIND>::value],
-                                      const T (&tipR)[Radius<KIND>::value], const Consts<T>& k) {
+                                      const T (&tipR)[Radius<KIND>::value], const Consts<T>& k,
+                                      wave::Ends e = wave::Ends{}) {
   constexpr int S = Radius<KIND>::value;
   constexpr int B = R / S;
   const bool mL0 = lane == 31 - b, mL1 = lane == 30 - b;
@@ -72,22 +73,23 @@ __device__ __forceinline__ void v_blk(T (&A)[R], T (&Q)[R], const T (&buf)[R][2]
         const int rr = orr % R;
         row[rr] = wave::pick(orr >= R ? mR1 : mR0, buf[rr][j & 1], row[rr]);
       }
-      wave::tier<KIND, T, R, TIPS>(A, Q, ((j + 1) & 1) != 0, tipL, tipR, first, last, k);
+      wave::tier<KIND, T, R, TIPS, INS>(A, Q, ((j + 1) & 1) != 0, tipL, tipR, first, last, k, e);
     }
   }
 }
 
 // V tiers [t0, t1) with t0 a multiple of the block height: whole blocks, then
 // the guarded remainder (with the triangle tips when TIPS).
-template <int KIND, typename T, int R, bool TIPS>
+template <int KIND, typename T, int R, bool TIPS, bool INS = false>
 __device__ __forceinline__ void v_run(T (&A)[R], T (&Q)[R], const T (&buf)[R][2], int t0, int t1, int lane,
                                       const T (&tipL)[Radius<KIND>::value],
-                                      const T (&tipR)[Radius<KIND>::value], const Consts<T>& k) {
+                                      const T (&tipR)[Radius<KIND>::value], const Consts<T>& k,
+                                      wave::Ends e = wave::Ends{}) {
   constexpr int B = R / Radius<KIND>::value;
   if (t0 >= t1) return;
   const int bl = (t1 - 1) / B;  // block holding the last tier
-  for (int b = t0 / B; b < bl; ++b) v_blk<KIND, T, R, true, false>(A, Q, buf, b, t1, lane, tipL, tipR, k);
-  v_blk<KIND, T, R, false, TIPS>(A, Q, buf, bl, t1, lane, tipL, tipR, k);
+  for (int b = t0 / B; b < bl; ++b) v_blk<KIND, T, R, true, false, INS>(A, Q, buf, b, t1, lane, tipL, tipR, k, e);
+  v_blk<KIND, T, R, false, TIPS, INS>(A, Q, buf, bl, t1, lane, tipL, tipR, k, e);
 }
 
 // Lambda tiers of block b, counted from the base of the layout's own 64 R-
@@ -95,9 +97,9 @@ __device__ __forceinline__ void v_run(T (&A)[R], T (&Q)[R], const T (&buf)[R][2]
 // values of tier t ([S t, S t + 2S), lanes b and b+1; [64 R - S(t+2),
 // 64 R - S t), lanes 63-b and 62-b), then computes tier t+1 unless
 // t == tskip (the empty top of a full triangle; never inside a FULL block).
-template <int KIND, typename T, int R, bool FULL>
+template <int KIND, typename T, int R, bool FULL, bool INS = false>
 __device__ __forceinline__ void l_blk(T (&A)[R], T (&Q)[R], T (&buf)[R][2], int b, int t0, int t1, int tskip,
-                                      int lane, const Consts<T>& k) {
+                                      int lane, const Consts<T>& k, wave::Ends e = wave::Ends{}) {
   constexpr int S = Radius<KIND>::value;
   constexpr int B = R / S;
   const bool mL0 = lane == b, mL1 = lane == b + 1;
@@ -118,32 +120,55 @@ __device__ __forceinline__ void l_blk(T (&A)[R], T (&Q)[R], T (&buf)[R][2], int 
         buf[rr][j & 1] = wave::pick(orr < 0 ? mR1 : mR0, row[rr], buf[rr][j & 1]);
       }
       if (FULL || t != tskip)
-        wave::tier<KIND, T, R, false>(A, Q, ((j + 1) & 1) != 0, tip0, tip0, false, false, k);
+        wave::tier<KIND, T, R, false, INS>(A, Q, ((j + 1) & 1) != 0, tip0, tip0, false, false, k, e);
     }
   }
 }
 
 // Lambda tiers [t0, t1) of a layout: a guarded head block when t0 is not a
 // block boundary, whole blocks, then the guarded remainder.
-template <int KIND, typename T, int R>
+template <int KIND, typename T, int R, bool INS = false>
 __device__ __forceinline__ void l_run(T (&A)[R], T (&Q)[R], T (&buf)[R][2], int t0, int t1, int tskip, int lane,
-                                      const Consts<T>& k) {
+                                      const Consts<T>& k, wave::Ends e = wave::Ends{}) {
   constexpr int B = R / Radius<KIND>::value;
   if (t1 <= t0) return;
   int b = t0 / B;
   const int bl = (t1 - 1) / B;
   if (t0 % B != 0 && b < bl) {
-    l_blk<KIND, T, R, false>(A, Q, buf, b, t0, t1, tskip, lane, k);
+    l_blk<KIND, T, R, false, INS>(A, Q, buf, b, t0, t1, tskip, lane, k, e);
     ++b;
   }
-  for (; b < bl; ++b) l_blk<KIND, T, R, true>(A, Q, buf, b, t0, t1, -1, lane, k);
-  l_blk<KIND, T, R, false>(A, Q, buf, bl, t0, t1, tskip, lane, k);
+  for (; b < bl; ++b) l_blk<KIND, T, R, true, INS>(A, Q, buf, b, t0, t1, -1, lane, k, e);
+  l_blk<KIND, T, R, false, INS>(A, Q, buf, bl, t0, t1, tskip, lane, k, e);
+}
+
+// Where a tile of an insulated rod holds the rod's ends (all false for the
+// tiles in between): `seam` -- the ends meet at the tile middle (the shifted
+// tiling's tile across the ring seam: node n-1 is point 32P-1, node 0 is
+// point 32P); `lo` -- node 0 is the tile's first point; `hi` -- node n-1 is
+// its last point.
+struct Bnd {
+  bool seam = false;
+  bool lo = false;
+  bool hi = false;
+};
+
+// Lanes of layout R (window centred on the tile middle) holding an end: the
+// middle is lane 31's last and lane 32's first point in every layout; the
+// tile's first and last points are in the full layout only.
+template <int P, int R>
+__device__ __forceinline__ wave::Ends ends_of(const Bnd& bd, int lane) {
+  wave::Ends e;
+  e.left = (bd.seam && lane == 32) || (R == P && bd.lo && lane == 0);
+  e.right = (bd.seam && lane == 31) || (R == P && bd.hi && lane == 63);
+  return e;
 }
 
 // V layouts R, R + step, .., P - step.  `done` counts the V tiers already
 // computed; the row travels between layouts through stg.
-template <int KIND, typename T, int P, int R>
-__device__ __forceinline__ void v_narrow(T* sb, T* stg, int hv, int& done, int lane, const Consts<T>& k) {
+template <int KIND, typename T, int P, int R, bool INS = false>
+__device__ __forceinline__ void v_narrow(T* sb, T* stg, int hv, int& done, int lane, const Consts<T>& k,
+                                         const Bnd& bd = Bnd{}) {
   if constexpr (R < P) {
     constexpr int S = Radius<KIND>::value;
     // The layout holds the tiers whose band fits, S (t + 2) <= 32 R; it hands
@@ -162,22 +187,22 @@ __device__ __forceinline__ void v_narrow(T* sb, T* stg, int hv, int& done, int l
         buf[r][1] = sb[pad(2 * (xl + r + S) + 1)];
       }
       const T tip0[S] = {};
-      v_run<KIND, T, R, false>(A, Q, buf, done, tend, lane, tip0, tip0, k);
+      v_run<KIND, T, R, false, INS>(A, Q, buf, done, tend, lane, tip0, tip0, k, ends_of<P, R>(bd, lane));
       done = tend;
       __syncthreads();  // every lane has read its row before the row is rewritten
 #pragma unroll
       for (int r = 0; r < R; ++r) stg[pad(xl + r)] = A[r];
       __syncthreads();
     }
-    v_narrow<KIND, T, P, R + Step<KIND>::value>(sb, stg, hv, done, lane, k);
+    v_narrow<KIND, T, P, R + Step<KIND>::value, INS>(sb, stg, hv, done, lane, k, bd);
   }
 }
 
 // Lambda layouts R, R - step, .., step, entered at tier `done` (a multiple of
 // 32 step / S, where the triangle first fits the next narrower layout).
-template <int KIND, typename T, int P, int R>
+template <int KIND, typename T, int P, int R, bool INS = false>
 __device__ __forceinline__ void l_narrow(T* sb, T* stg, int hl, bool empty_top, int& done, int lane,
-                                         const Consts<T>& k) {
+                                         const Consts<T>& k, const Bnd& bd = Bnd{}) {
   if constexpr (R > 0) {
     constexpr int S = Radius<KIND>::value;
     constexpr int ST = Step<KIND>::value;
@@ -196,7 +221,7 @@ __device__ __forceinline__ void l_narrow(T* sb, T* stg, int hl, bool empty_top, 
       }
       // entered at its first tier (done == kFirst): virtual tiers from 0
       const int tskip = empty_top ? hl - 1 - kFirst : -1;
-      l_run<KIND, T, R>(A, Q, buf, 0, tend - kFirst, tskip, lane, k);
+      l_run<KIND, T, R, INS>(A, Q, buf, 0, tend - kFirst, tskip, lane, k, ends_of<P, R>(bd, lane));
       done = tend;
       if (done >= hl && !empty_top) {
         // flat top of the trapezoid: the row at its top tier
@@ -220,16 +245,17 @@ __device__ __forceinline__ void l_narrow(T* sb, T* stg, int hl, bool empty_top, 
       }
       __syncthreads();
     }
-    l_narrow<KIND, T, P, R - ST>(sb, stg, hl, empty_top, done, lane, k);
+    l_narrow<KIND, T, P, R - ST, INS>(sb, stg, hl, empty_top, done, lane, k, bd);
   }
 }
 
 // ROLE: 0 up-triangle (hv == 0), 1 diamond, 2 down-triangle (hl == 0).  The
 // tile is 64 P points from `origin`, seam at 32 P; sL/sR are its left and
-// right edge slots (layout as in wave_tile.h with kL = kR = 32).
-template <int KIND, typename T, int P, int ROLE>
+// right edge slots (layout as in wave_tile.h with kL = kR = 32).  INS: heat on
+// an insulated rod, with the rod's ends in this tile where `bd` says.
+template <int KIND, typename T, int P, int ROLE, bool INS = false>
 __device__ __forceinline__ void tile_phase(T* u, int64_t n, int64_t origin, T* sL, T* sR, int hv, int hl,
-                                           const Consts<T>& k, int lane, T* sb, T* stg) {
+                                           const Consts<T>& k, int lane, T* sb, T* stg, const Bnd& bd = Bnd{}) {
   constexpr int S = Radius<KIND>::value;
   constexpr int B = P / S;
   constexpr int W = 64 * P;
@@ -273,7 +299,7 @@ __device__ __forceinline__ void tile_phase(T* u, int64_t n, int64_t origin, T* s
     }
     __syncthreads();
     int done = 0;
-    v_narrow<KIND, T, P, ST>(sb, stg, hv, done, lane, k);
+    v_narrow<KIND, T, P, ST, INS>(sb, stg, hv, done, lane, k, bd);
 #pragma unroll
     for (int r = 0; r < P; ++r) {
       A[r] = done > 0 ? stg[pad(lane * P + r)] : T(0);
@@ -288,7 +314,7 @@ __device__ __forceinline__ void tile_phase(T* u, int64_t n, int64_t origin, T* s
       tipL[i] = sb[pad(2 * i + tp)];
       tipR[i] = sb[pad(2 * (W + S + i) + tp)];
     }
-    v_run<KIND, T, P, true>(A, Q, buf, done, hv, lane, tipL, tipR, k);
+    v_run<KIND, T, P, true, INS>(A, Q, buf, done, hv, lane, tipL, tipR, k, ends_of<P, P>(bd, lane));
     // flat tops of the producer trapezoids: tile points outside the gap
     if (S * hv < HALF) {
 #pragma unroll
@@ -317,7 +343,7 @@ __device__ __forceinline__ void tile_phase(T* u, int64_t n, int64_t origin, T* s
     constexpr int kNext = P > ST ? 32 * ST / S : 1 << 30;
     const int tend = hl < kNext ? hl : kNext;
     const int tskip = empty_top ? hl - 1 : -1;
-    l_run<KIND, T, P>(A, Q, buf, 0, tend, tskip, lane, k);
+    l_run<KIND, T, P, INS>(A, Q, buf, 0, tend, tskip, lane, k, ends_of<P, P>(bd, lane));
     int done = tend;
     if (done >= hl && !empty_top) {
 #pragma unroll
@@ -338,7 +364,7 @@ __device__ __forceinline__ void tile_phase(T* u, int64_t n, int64_t origin, T* s
       if (done < hl) stg[pad(lane * P + r)] = A[r];
     }
     __syncthreads();
-    l_narrow<KIND, T, P, P - ST>(sb, stg, hl, empty_top, done, lane, k);
+    l_narrow<KIND, T, P, P - ST, INS>(sb, stg, hl, empty_top, done, lane, k, bd);
     // outgoing slots: producer left side p = x (x < HALF + S), right side
     // p = x - HALF + S (x >= HALF - S)
     {

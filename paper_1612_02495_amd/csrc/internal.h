@@ -57,6 +57,13 @@ template <int KIND, typename T>
 hipError_t launch_phase_compact(const PhaseArgs& a, const Consts<T>& k, hipStream_t st);
 // Whether the compacted wave engine has a kernel for this kind and width.
 bool compact_engine_supports(int kind, int w);
+// Heat on a rod with insulated ends (compacted engine; widths as for heat).
+template <typename T>
+hipError_t launch_phase_compact_insulated(const PhaseArgs& a, const Consts<T>& k, hipStream_t st);
+
+// Naive heat step on a rod with insulated ends (mirror ghosts at nodes 0, n-1).
+template <typename T>
+hipError_t launch_naive_heat_insulated(const T* in, T* out, int64_t n, const Consts<T>& k, hipStream_t st);
 
 // Record the calling thread's last error (swept_last_error) and return code.
 int set_error(int code, const std::string& msg);

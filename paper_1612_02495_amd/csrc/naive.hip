@@ -22,6 +22,18 @@ naive_heat_kernel(const T* __restrict__ in, T* __restrict__ out, int64_t n, Cons
   out[i] = heat_update(in[wrap_once(i - 1, n)], in[i], in[wrap_once(i + 1, n)], k);
 }
 
+// Insulated rod (Sec. 4.1): nodes 0 and n-1 take the mirror ghost about
+// themselves, u_{-1} = u_1 and u_n = u_{n-2}.
+template <typename T>
+__global__ void __launch_bounds__(kNaiveThreads)
+naive_heat_insulated_kernel(const T* __restrict__ in, T* __restrict__ out, int64_t n, Consts<T> k) {
+  const int64_t i = (int64_t)blockIdx.x * kNaiveThreads + threadIdx.x;
+  if (i >= n) return;
+  const T left = in[i == 0 ? 1 : i - 1];
+  const T right = in[i == n - 1 ? n - 2 : i + 1];
+  out[i] = heat_update(left, in[i], right, k);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kNaiveThreads)
 naive_ks_predictor_kernel(const T* __restrict__ u, T* __restrict__ q, int64_t n, Consts<T> k) {
@@ -51,6 +63,12 @@ hipError_t launch_naive_heat(const T* in, T* out, int64_t n, const Consts<T>& k,
 }
 
 template <typename T>
+hipError_t launch_naive_heat_insulated(const T* in, T* out, int64_t n, const Consts<T>& k, hipStream_t st) {
+  hipLaunchKernelGGL(naive_heat_insulated_kernel<T>, grid_for(n), dim3(kNaiveThreads), 0, st, in, out, n, k);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_naive_ks_predictor(const T* u, T* q, int64_t n, const Consts<T>& k, hipStream_t st) {
   hipLaunchKernelGGL(naive_ks_predictor_kernel<T>, grid_for(n), dim3(kNaiveThreads), 0, st, u, q, n, k);
   return hipGetLastError();
@@ -64,6 +82,10 @@ hipError_t launch_naive_ks_final(T* u, const T* q, int64_t n, const Consts<T>& k
 
 template hipError_t launch_naive_heat<float>(const float*, float*, int64_t, const Consts<float>&, hipStream_t);
 template hipError_t launch_naive_heat<double>(const double*, double*, int64_t, const Consts<double>&, hipStream_t);
+template hipError_t launch_naive_heat_insulated<float>(const float*, float*, int64_t, const Consts<float>&,
+                                                        hipStream_t);
+template hipError_t launch_naive_heat_insulated<double>(const double*, double*, int64_t, const Consts<double>&,
+                                                         hipStream_t);
 template hipError_t launch_naive_ks_predictor<float>(const float*, float*, int64_t, const Consts<float>&, hipStream_t);
 template hipError_t launch_naive_ks_predictor<double>(const double*, double*, int64_t, const Consts<double>&, hipStream_t);
 template hipError_t launch_naive_ks_final<float>(float*, const float*, int64_t, const Consts<float>&, hipStream_t);

@@ -1,14 +1,18 @@
-// Compacted wave engine for one periodic grid: one wave64 per tile as in the
-// register engine (phase_wave.hip), with each run of tiers laid out over the
-// part of the tile it touches (compact_tile.h).  Tiles, slots and phase
-// parities are those of the other engines, so all three can run alternate
-// phases of one run.
+// Compacted wave engine for one periodic grid (or one insulated rod): one
+// wave64 per tile as in the register engine (phase_wave.hip), with each run
+// of tiers laid out over the part of the tile it touches (compact_tile.h).
+// Tiles, slots and phase parities are those of the other engines, so all
+// three can run alternate phases of one run.
 #include "compact_tile.h"
 
 namespace swept {
 namespace {
 
-template <int KIND, typename T, int P, int ROLE>
+// INS: heat on a rod with insulated ends.  The rod's nodes 0 and n-1 sit at
+// the ring seam: at the middle of the last tile of the shifted tiling
+// (parity 1), or at the first point of tile 0 and the last of tile nt-1
+// (parity 0).  Only those tiles run the tier code with the mirror ghosts.
+template <int KIND, typename T, int P, int ROLE, bool INS>
 __global__ void __launch_bounds__(64)
 phase_compact_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, int hl, Consts<T> k) {
   constexpr int S = Radius<KIND>::value;
@@ -21,13 +25,23 @@ phase_compact_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, 
   const int64_t origin = j * (int64_t)W + (parity ? HALF : 0);
   T* sL = parity ? slots + (nt + j) * SLEN : slots + j * SLEN;
   T* sR = parity ? slots + ((j + 1) % nt) * SLEN : slots + (nt + j) * SLEN;
+  if constexpr (INS) {
+    compact::Bnd bd;
+    bd.seam = parity && j == nt - 1;
+    bd.lo = !parity && j == 0;
+    bd.hi = !parity && j == nt - 1;
+    if (bd.seam || bd.lo || bd.hi) {
+      compact::tile_phase<KIND, T, P, ROLE, true>(u, n, origin, sL, sR, hv, hl, k, (int)threadIdx.x, sb, stg, bd);
+      return;
+    }
+  }
   compact::tile_phase<KIND, T, P, ROLE>(u, n, origin, sL, sR, hv, hl, k, (int)threadIdx.x, sb, stg);
 }
 
-template <int KIND, typename T, int P>
+template <int KIND, typename T, int P, bool INS>
 hipError_t launch_p(const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
-  auto kern = a.hv == 0 ? phase_compact_kernel<KIND, T, P, 0>
-              : (a.hl == 0 ? phase_compact_kernel<KIND, T, P, 2> : phase_compact_kernel<KIND, T, P, 1>);
+  auto kern = a.hv == 0 ? phase_compact_kernel<KIND, T, P, 0, INS>
+              : (a.hl == 0 ? phase_compact_kernel<KIND, T, P, 2, INS> : phase_compact_kernel<KIND, T, P, 1, INS>);
   hipLaunchKernelGGL(kern, dim3((unsigned)a.nt), dim3(64), 0, st, static_cast<T*>(a.u), static_cast<T*>(a.slots),
                      a.n, a.nt, a.parity, a.hv, a.hl, k);
   return hipGetLastError();
@@ -47,9 +61,23 @@ hipError_t launch_phase_compact(const PhaseArgs& a, const Consts<T>& k, hipStrea
   if (!compact_engine_supports(KIND, a.w)) return hipErrorInvalidValue;
   switch (a.w / 64) {
     case 8:
-      return launch_p<KIND, T, 8>(a, k, st);
+      return launch_p<KIND, T, 8, false>(a, k, st);
     case 16:
-      return launch_p<KIND, T, 16>(a, k, st);
+      return launch_p<KIND, T, 16, false>(a, k, st);
+    default:
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_phase_compact_insulated(const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
+  if (!compact_engine_supports(kHeat, a.w)) return hipErrorInvalidValue;
+  switch (a.w / 64) {
+    case 8:
+      return launch_p<kHeat, T, 8, true>(a, k, st);
+    case 16:
+      return launch_p<kHeat, T, 16, true>(a, k, st);
     default:
       break;
   }
@@ -60,5 +88,7 @@ template hipError_t launch_phase_compact<kHeat, float>(const PhaseArgs&, const C
 template hipError_t launch_phase_compact<kHeat, double>(const PhaseArgs&, const Consts<double>&, hipStream_t);
 template hipError_t launch_phase_compact<kKS, float>(const PhaseArgs&, const Consts<float>&, hipStream_t);
 template hipError_t launch_phase_compact<kKS, double>(const PhaseArgs&, const Consts<double>&, hipStream_t);
+template hipError_t launch_phase_compact_insulated<float>(const PhaseArgs&, const Consts<float>&, hipStream_t);
+template hipError_t launch_phase_compact_insulated<double>(const PhaseArgs&, const Consts<double>&, hipStream_t);
 
 }  // namespace swept

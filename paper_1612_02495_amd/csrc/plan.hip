@@ -32,6 +32,14 @@ int hip_fail(hipError_t e, const char* what) {
 
 int radius_of(int kind) { return kind == SWEPT_KS_RK2 ? 2 : 1; }
 
+bool valid_kind(int kind) {
+  return kind == SWEPT_HEAT_FTCS || kind == SWEPT_KS_RK2 || kind == SWEPT_HEAT_INSULATED;
+}
+
+// The stencil a kind runs (the insulated rod is the heat stencil with mirror
+// ghosts at its two end nodes).
+int stencil_of(int kind) { return kind == SWEPT_KS_RK2 ? swept::kKS : swept::kHeat; }
+
 constexpr int kMinTile = 4;
 constexpr int kMaxTile = 4096;
 
@@ -120,9 +128,13 @@ namespace {
 
 size_t elem_size(int dtype) { return dtype == SWEPT_F64 ? sizeof(double) : sizeof(float); }
 
+// The insulated rod has kernels in the compacted engine only.
 bool engine_supports(int engine, int kind, int w) {
-  if (engine == SWEPT_ENGINE_WAVE) return swept::wave_engine_supports(kind, w);
-  if (engine == SWEPT_ENGINE_COMPACT) return swept::compact_engine_supports(kind, w);
+  const int st = stencil_of(kind);
+  if (kind == SWEPT_HEAT_INSULATED)
+    return (engine == SWEPT_ENGINE_COMPACT || engine == SWEPT_ENGINE_AUTO) && swept::compact_engine_supports(st, w);
+  if (engine == SWEPT_ENGINE_WAVE) return swept::wave_engine_supports(st, w);
+  if (engine == SWEPT_ENGINE_COMPACT) return swept::compact_engine_supports(st, w);
   return true;
 }
 
@@ -130,8 +142,9 @@ bool engine_supports(int engine, int kind, int w) {
 // engine where it has a kernel, else the register engine, else LDS.
 int resolved_engine(const swept_plan_s* p) {
   if (p->engine != SWEPT_ENGINE_AUTO) return p->engine;
-  if (swept::compact_engine_supports(p->kind, p->w)) return SWEPT_ENGINE_COMPACT;
-  return swept::wave_engine_supports(p->kind, p->w) ? SWEPT_ENGINE_WAVE : SWEPT_ENGINE_LDS;
+  const int st = stencil_of(p->kind);
+  if (swept::compact_engine_supports(st, p->w)) return SWEPT_ENGINE_COMPACT;
+  return swept::wave_engine_supports(st, p->w) ? SWEPT_ENGINE_WAVE : SWEPT_ENGINE_LDS;
 }
 
 template <int KIND, typename T>
@@ -148,6 +161,7 @@ hipError_t launch_phase(const swept_plan_s* p, const PhaseArgs& a, const Consts<
 
 template <typename T>
 hipError_t dispatch_phase(const swept_plan_s* p, const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
+  if (p->kind == SWEPT_HEAT_INSULATED) return swept::launch_phase_compact_insulated<T>(a, k, st);
   if (p->kind == SWEPT_HEAT_FTCS) return launch_phase<swept::kHeat, T>(p, a, k, st);
   return launch_phase<swept::kKS, T>(p, a, k, st);
 }
@@ -156,11 +170,12 @@ template <typename T>
 hipError_t run_naive(const swept_plan_s* p, T* u, int64_t steps, const Consts<T>& k, hipStream_t st) {
   T* buf = static_cast<T*>(p->buf);
   hipError_t e = hipSuccess;
-  if (p->kind == SWEPT_HEAT_FTCS) {
+  if (p->kind != SWEPT_KS_RK2) {
     T* cur = u;
     T* nxt = buf;
     for (int64_t m = 0; m < steps; ++m) {
-      e = swept::launch_naive_heat<T>(cur, nxt, p->n, k, st);
+      e = p->kind == SWEPT_HEAT_INSULATED ? swept::launch_naive_heat_insulated<T>(cur, nxt, p->n, k, st)
+                                          : swept::launch_naive_heat<T>(cur, nxt, p->n, k, st);
       if (e != hipSuccess) return e;
       T* t = cur;
       cur = nxt;
@@ -183,7 +198,9 @@ int choose_tile(int kind, int64_t n) {
   // the benchmark refines this per workload).
   std::string why;
   for (int w = 1024; w >= kMinTile; w >>= 1) {
-    if (n % w == 0 && n >= w && tile_ok(kind, w, &why)) return w;
+    if (n % w == 0 && n >= w && tile_ok(kind, w, &why) &&
+        (kind != SWEPT_HEAT_INSULATED || engine_supports(SWEPT_ENGINE_COMPACT, kind, w)))
+      return w;
   }
   return 0;
 }
@@ -196,7 +213,7 @@ const char* swept_last_error(void) { return g_last_error.c_str(); }
 
 int swept_schedule(int kind, int tile_width, int steps_per_cycle, int64_t steps, int32_t* heights,
                    int64_t cap, int64_t* count) {
-  if (kind != SWEPT_HEAT_FTCS && kind != SWEPT_KS_RK2) return fail(SWEPT_EINVAL, "unknown stencil kind");
+  if (!valid_kind(kind)) return fail(SWEPT_EINVAL, "unknown stencil kind");
   std::string why;
   if (!tile_ok(kind, tile_width, &why)) return fail(SWEPT_EINVAL, why);
   const int hfull = full_tiers(kind, tile_width);
@@ -216,7 +233,7 @@ int swept_schedule(int kind, int tile_width, int steps_per_cycle, int64_t steps,
 
 int swept_tile_geometry(int kind, int tile_width, int* full_tiers_out, int* row_values,
                         int* edge_slot_values) {
-  if (kind != SWEPT_HEAT_FTCS && kind != SWEPT_KS_RK2) return fail(SWEPT_EINVAL, "unknown stencil kind");
+  if (!valid_kind(kind)) return fail(SWEPT_EINVAL, "unknown stencil kind");
   std::string why;
   if (!tile_ok(kind, tile_width, &why)) return fail(SWEPT_EINVAL, why);
   const int s = radius_of(kind);
@@ -230,11 +247,11 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
                       int tile_width, int steps_per_cycle) {
   if (!out) return fail(SWEPT_EINVAL, "out must not be NULL");
   *out = nullptr;
-  if (kind != SWEPT_HEAT_FTCS && kind != SWEPT_KS_RK2) return fail(SWEPT_EINVAL, "unknown stencil kind");
+  if (!valid_kind(kind)) return fail(SWEPT_EINVAL, "unknown stencil kind");
   if (dtype != SWEPT_F32 && dtype != SWEPT_F64) return fail(SWEPT_EINVAL, "unknown dtype");
   if (n < kMinTile) return fail(SWEPT_EINVAL, "n must be >= 4");
   if (!is_finite(dt) || !is_finite(dx) || dx == 0.0) return fail(SWEPT_EINVAL, "dt and dx must be finite, dx != 0");
-  if (kind == SWEPT_HEAT_FTCS && !is_finite(alpha)) return fail(SWEPT_EINVAL, "alpha must be finite");
+  if (kind != SWEPT_KS_RK2 && !is_finite(alpha)) return fail(SWEPT_EINVAL, "alpha must be finite");
   if (tile_width < 0) return fail(SWEPT_EINVAL, "tile_width must be >= 0");
   int w = tile_width;
   std::string why;
@@ -257,6 +274,8 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
     return fail(SWEPT_EINVAL, why);
   }
   if (n % w != 0 || n < w) return fail(SWEPT_EUNSUPPORTED, "n must be a positive multiple of tile_width");
+  if (kind == SWEPT_HEAT_INSULATED && !engine_supports(SWEPT_ENGINE_COMPACT, kind, w))
+    return fail(SWEPT_EUNSUPPORTED, "the insulated rod runs on the compacted engine: tile_width 512 or 1024");
   const int hfull = full_tiers(kind, w);
   const int tps = tiers_per_step(kind);
   if (steps_per_cycle < 0 || steps_per_cycle * tps > hfull)
@@ -300,13 +319,13 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
     return hip_fail(e, "hipDeviceGetAttribute");
   }
   size_t lds = 0;
-  if (kind == SWEPT_HEAT_FTCS)
+  if (kind != SWEPT_KS_RK2)
     lds = dtype == SWEPT_F64 ? swept::phase_lds_bytes<swept::kHeat, double>(w)
                              : swept::phase_lds_bytes<swept::kHeat, float>(w);
   else
     lds = dtype == SWEPT_F64 ? swept::phase_lds_bytes<swept::kKS, double>(w)
                              : swept::phase_lds_bytes<swept::kKS, float>(w);
-  if (lds > (size_t)max_lds && !swept::wave_engine_supports(kind, w)) {
+  if (lds > (size_t)max_lds && !swept::wave_engine_supports(stencil_of(kind), w)) {
     delete p;
     return fail(SWEPT_EUNSUPPORTED, "tile too wide for the LDS of this device");
   }
@@ -338,10 +357,10 @@ int swept_plan_set_engine(swept_plan p, int engine) {
   if (engine != SWEPT_ENGINE_AUTO && engine != SWEPT_ENGINE_LDS && engine != SWEPT_ENGINE_WAVE &&
       engine != SWEPT_ENGINE_COMPACT)
     return fail(SWEPT_EINVAL, "unknown engine");
-  if (engine == SWEPT_ENGINE_WAVE && !swept::wave_engine_supports(p->kind, p->w))
-    return fail(SWEPT_EUNSUPPORTED, "no wave-resident kernel for this kind and tile width");
-  if (engine == SWEPT_ENGINE_COMPACT && !swept::compact_engine_supports(p->kind, p->w))
-    return fail(SWEPT_EUNSUPPORTED, "no compacted kernel for this kind and tile width");
+  if (!engine_supports(engine, p->kind, p->w))
+    return fail(SWEPT_EUNSUPPORTED, engine == SWEPT_ENGINE_WAVE      ? "no wave-resident kernel for this kind and tile width"
+                                    : engine == SWEPT_ENGINE_COMPACT ? "no compacted kernel for this kind and tile width"
+                                                                     : "no kernel of this engine for this kind");
   if (engine == SWEPT_ENGINE_LDS && !p->lds_fits)
     return fail(SWEPT_EUNSUPPORTED, "tile too wide for the LDS of this device");
   p->engine = engine;
@@ -408,7 +427,7 @@ int naive_run(swept_plan p, void* u, int64_t steps, void* stream) {
 
 int swept_autotune_lookup(int64_t n, int kind, int dtype, int* tile_width, int* steps_per_cycle, int* engine,
                           double* ns_per_cell_update) {
-  if (kind != SWEPT_HEAT_FTCS && kind != SWEPT_KS_RK2) return fail(SWEPT_EINVAL, "unknown stencil kind");
+  if (!valid_kind(kind)) return fail(SWEPT_EINVAL, "unknown stencil kind");
   if (dtype != SWEPT_F32 && dtype != SWEPT_F64) return fail(SWEPT_EINVAL, "unknown dtype");
   swept::TuneEntry te;
   if (!swept::tune_lookup(kind, dtype, n, &te)) return fail(SWEPT_EUNSUPPORTED, "no tuned entry for this problem");
@@ -424,7 +443,7 @@ void swept_autotune_forget(void) { swept::tune_forget_all(); }
 int swept_autotune(int64_t n, int kind, int dtype, double dt, double dx, double alpha, int64_t steps,
                    swept_tune_result* results, int cap, int* count, int* tile_width, int* steps_per_cycle,
                    int* engine) {
-  if (kind != SWEPT_HEAT_FTCS && kind != SWEPT_KS_RK2) return fail(SWEPT_EINVAL, "unknown stencil kind");
+  if (!valid_kind(kind)) return fail(SWEPT_EINVAL, "unknown stencil kind");
   if (dtype != SWEPT_F32 && dtype != SWEPT_F64) return fail(SWEPT_EINVAL, "unknown dtype");
   if (n < kMinTile) return fail(SWEPT_EINVAL, "n must be >= 4");
   if (steps < 0) return fail(SWEPT_EINVAL, "steps must be >= 0");

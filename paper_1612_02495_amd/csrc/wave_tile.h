@@ -81,20 +81,34 @@ __device__ __forceinline__ T at(const T (&row)[P], const T (&lo)[S], const T (&h
   return row[o];
 }
 
+// Lanes holding an end of an insulated rod (heat only): `left` marks the
+// lane whose first point is node 0, `right` the lane whose last point is node
+// n-1.  Their missing neighbour is the mirror ghost about the end node.
+struct Ends {
+  bool left = false;
+  bool right = false;
+};
+
 // Advance the tile from tier t to tier t+1.  Heat: one row A.  KS: A holds
-// even tiers (finals), Q odd tiers (predictors).
-template <int KIND, typename T, int P, bool TIPS>
+// even tiers (finals), Q odd tiers (predictors).  INS (heat): the lanes of
+// `e` take the mirror ghost at the rod's ends, u_{-1} = u_1, u_n = u_{n-2}.
+template <int KIND, typename T, int P, bool TIPS, bool INS = false>
 __device__ __forceinline__ void tier(T (&A)[P], T (&Q)[P], bool t1_odd, const T (&tipL)[Radius<KIND>::value],
                                      const T (&tipR)[Radius<KIND>::value], bool first, bool last,
-                                     const Consts<T>& k) {
+                                     const Consts<T>& k, Ends e = Ends{}) {
   constexpr int S = Radius<KIND>::value;
+  static_assert(!INS || (KIND == kHeat && P >= 2), "insulated ends: heat, two or more points per lane");
   T lo[S], hi[S];
   if constexpr (KIND == kHeat) {
     halos<T, P, S, TIPS>(A, tipL, tipR, first, last, lo, hi);
     T prev = lo[0];
+    if constexpr (INS) prev = pick(e.left, A[1], prev);
 #pragma unroll
     for (int r = 0; r < P; ++r) {
-      const T right = r == P - 1 ? hi[0] : A[r + 1];
+      T right = r == P - 1 ? hi[0] : A[r + 1];
+      if constexpr (INS) {
+        if (r == P - 1) right = pick(e.right, prev, right);
+      }
       const T nv = heat_update(prev, A[r], right, k);
       prev = A[r];
       A[r] = nv;

@@ -18,6 +18,10 @@ Sec. 4.1):
                    u0 = cos(x/16)(1+sin(x/16)) + 1e-3 N(0,1).
 * ``heat_batch``   independent periodic heat problems with N log-uniform in
                    [2^8, 2^16], Fo ~ U(0.05, 0.45), mode-sum initial states.
+* ``heat_rod``     the rod with insulated ends of Sec. 4.1: n nodes on [0, 1]
+                   (dx = 1/(n-1)), alpha=1, dt=dx^2/4 (Fo=1/4 exactly), an
+                   initial temperature gradient u0 = x plus 8 cosine modes
+                   with amplitudes 0.1 U(-1,1).
 * ``heat_adjoint`` batch of N=2^18 heat problems, dt=dx^2 so Fo = alpha,
                    alpha ~ U(0.05, 0.45), mode-sum u0, target from a
                    perturbed forward run.
@@ -84,6 +88,21 @@ def heat_large(seed: int = 1, n: int = 2 ** 20, steps: int = 100000) -> Problem:
     rng = _rng(seed)
     u0, ks_, amps = mode_sum(n, rng)
     return Problem("heat", n, dt, dx, 1.0, steps, u0, modes=ks_, amps=amps)
+
+
+def heat_rod(n: int = 2 ** 20, seed: int = 8, steps: int = 100000) -> Problem:
+    """Insulated rod (Sec. 4.1): a temperature gradient plus cosine modes,
+    which are the rod's own eigenmodes (cos(pi k i/(n-1)))."""
+    dx = 1.0 / (n - 1)
+    dt = dx * dx / 4.0
+    rng = _rng(seed)
+    i = np.arange(n, dtype=np.float64)
+    ks_ = rng.choice(np.arange(1, max(2, n // 8)), size=min(8, max(1, n // 8 - 1)), replace=False)
+    amps = 0.1 * rng.uniform(-1.0, 1.0, size=ks_.size)
+    u0 = i * dx
+    for a, k in zip(amps, ks_):
+        u0 = u0 + a * np.cos(np.pi * k * i / (n - 1))
+    return Problem("heat_insulated", n, dt, dx, 1.0, steps, u0, modes=ks_, amps=amps)
 
 
 def ks(n: int = 2 ** 16, seed: int = 2, steps: int = 20000) -> Problem:

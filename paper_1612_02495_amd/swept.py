@@ -11,9 +11,9 @@ import numpy as np
 
 from . import _lib
 from ._lib import (SWEPT_ENGINE_AUTO, SWEPT_ENGINE_COMPACT, SWEPT_ENGINE_LDS, SWEPT_ENGINE_WAVE, SWEPT_F32, SWEPT_F64,
-                   SWEPT_HEAT_FTCS, SWEPT_KS_RK2, SweptError, check)
+                   SWEPT_HEAT_FTCS, SWEPT_HEAT_INSULATED, SWEPT_KS_RK2, SweptError, check)
 
-KINDS = {"heat": SWEPT_HEAT_FTCS, "ks": SWEPT_KS_RK2}
+KINDS = {"heat": SWEPT_HEAT_FTCS, "ks": SWEPT_KS_RK2, "heat_insulated": SWEPT_HEAT_INSULATED}
 ENGINES = {"auto": SWEPT_ENGINE_AUTO, "lds": SWEPT_ENGINE_LDS, "wave": SWEPT_ENGINE_WAVE,
            "compact": SWEPT_ENGINE_COMPACT}
 

@@ -57,6 +57,9 @@ def _create(n=1024, kind=0, dtype=1, dt=1e-6, dx=1e-3, alpha=1.0, w=64, spc=0):
     (dict(n=1023, w=0), _lib.SWEPT_EUNSUPPORTED),  # odd n: no tile width
     (dict(spc=33), _lib.SWEPT_EINVAL),          # heat w=64: at most 32 steps per phase
     (dict(kind=1, w=64, spc=9), _lib.SWEPT_EINVAL),  # KS w=64: at most 8 steps per phase
+    (dict(kind=3), _lib.SWEPT_EINVAL),
+    (dict(kind=2, w=64), _lib.SWEPT_EUNSUPPORTED),   # insulated rod: tile_width 512 or 1024 only
+    (dict(kind=2, alpha=float("nan")), _lib.SWEPT_EINVAL),
 ])
 def test_plan_create_rejects_before_any_device_call(kw, code):
     rc, h = _create(**kw)
@@ -135,3 +138,10 @@ def test_edge_slot_geometry():
             geo = P.swept_tile_geometry(kind, w)
             assert geo["edge_slot_values"] == 2 * (w // 2 + s)
             assert geo["row_values"] == w + 2 * s
+
+
+def test_insulated_rod_shares_the_heat_tiling():
+    # the insulated rod runs the heat stencil on the same ring of tiles
+    for w in (512, 1024):
+        assert P.swept_tile_geometry("heat_insulated", w) == P.swept_tile_geometry("heat", w)
+        assert P.swept_schedule("heat_insulated", w, 0, 1000) == P.swept_schedule("heat", w, 0, 1000)
