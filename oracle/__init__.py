@@ -53,9 +53,10 @@ def _load():
         lib.oracle_ks_f64.argtypes = [pd, i64, dbl, dbl, i64]
         lib.oracle_ks_f32.argtypes = [pf, i64, dbl, dbl, i64]
         lib.oracle_heat_adjoint_f64.argtypes = [pd, pd, i64, dbl, dbl, dbl, i64, i64, pd, pd, pd]
+        lib.oracle_ks_adjoint_f64.argtypes = [pd, pd, i64, dbl, dbl, i64, i64, pd, pd]
         for f in (lib.oracle_heat_f64, lib.oracle_heat_f32, lib.oracle_heat_insulated_f64,
                   lib.oracle_heat_insulated_f32, lib.oracle_ks_f64, lib.oracle_ks_f32,
-                  lib.oracle_heat_adjoint_f64):
+                  lib.oracle_heat_adjoint_f64, lib.oracle_ks_adjoint_f64):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -120,3 +121,17 @@ def heat_adjoint(u0, y, alpha: float, dt: float, dx: float, steps: int, ckpt: in
                                        int(steps), int(ckpt), _ptr(g), ctypes.byref(ga),
                                        ctypes.byref(jj)), "oracle_heat_adjoint")
     return jj.value, g, ga.value
+
+
+def ks_adjoint(u0, y, dt: float, dx: float, steps: int, ckpt: int = 0):
+    """Returns (J, dJ/du0) for J = 1/2 ||u_T - y||^2, periodic KS RK2, FP64."""
+    lib = _load()
+    a = _arr(u0, np.float64)
+    yy = _arr(y, np.float64)
+    if yy.size != a.size:
+        raise ValueError("u0 and y differ in size")
+    g = np.zeros_like(a)
+    J = ctypes.c_double()
+    _check(lib.oracle_ks_adjoint_f64(_ptr(a), _ptr(yy), a.size, float(dt), float(dx), int(steps), int(ckpt),
+                                     _ptr(g), ctypes.byref(J)), "oracle_ks_adjoint")
+    return J.value, g

@@ -318,3 +318,91 @@ int oracle_heat_adjoint_f64(const double* u0, const double* y, int64_t n, double
     free(ck); free(seg); free(lam); free(tmp);
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------- KS adjoint -- */
+/*
+ * Reverse sweep of the periodic KS RK2 scheme above for
+ * J = 1/2 ||u_T - y||^2 (not in the paper; plain calculus on the discrete
+ * scheme).  One step is q = u + (dt/2) f(u), u' = u + dt f(q), so with
+ * lambda' = dJ/du':
+ *   mu     = dt * Jf(q)^T lambda'                    (= dJ/dq)
+ *   lambda = lambda' + mu + (dt/2) * Jf(u)^T mu      (= dJ/du)
+ * where Jf(v) is the Jacobian of f at v.  Its transpose applied to w, at j,
+ * collects the derivatives of f_{j-2} .. f_{j+2} with respect to v_j:
+ *   df_{j-1}/dv_j = -( 2 v_j/(4dx) + 1/dx^2 - 4/dx^4)
+ *   df_{j+1}/dv_j = -(-2 v_j/(4dx) + 1/dx^2 - 4/dx^4)
+ *   df_j/dv_j     = -(-2/dx^2 + 6/dx^4)
+ *   df_{j+-2}/dv_j = -1/dx^4
+ * and the sum is taken in the order w_{j-1}, w_{j+1}, w_j, w_{j-2}, w_{j+2}.
+ * Forward states are recomputed from checkpoints every `ckpt` steps.
+ */
+static void ks_jt_f64(const double* v, const double* w, double* out, int64_t n, const ks_consts* k) {
+    double c1 = k->idx2 - 4.0 * k->idx4;
+    double c0 = -(6.0 * k->idx4 - 2.0 * k->idx2);
+    double c2 = -k->idx4;
+    for (int64_t j = 0; j < n; ++j) {
+        double s = 2.0 * v[j] * k->i4dx;
+        double dm = -(s + c1);  /* df_{j-1}/dv_j */
+        double dp = -(c1 - s);  /* df_{j+1}/dv_j */
+        out[j] = (((dm * w[wrap(j - 1, n)] + dp * w[wrap(j + 1, n)]) + c0 * w[j]) + c2 * w[wrap(j - 2, n)]) +
+                 c2 * w[wrap(j + 2, n)];
+    }
+}
+
+int oracle_ks_adjoint_f64(const double* u0, const double* y, int64_t n, double dt, double dx, int64_t steps,
+                          int64_t ckpt, double* g_u0, double* J) {
+    if (!u0 || !y || !g_u0 || !J || n < 5 || steps < 0) return ORACLE_EINVAL;
+    ks_consts k = ks_make(dt, dx);
+    int64_t K = ckpt;
+    if (K <= 0) {
+        K = 1;
+        while (K * K < steps) ++K;
+    }
+    int64_t nck = steps / K + 1;
+    double* cks = (double*)malloc((size_t)(nck * n) * sizeof(double));
+    double* seg = (double*)malloc((size_t)((K + 1) * n) * sizeof(double));
+    double* q = (double*)malloc((size_t)n * sizeof(double));
+    double* lam = (double*)malloc((size_t)n * sizeof(double));
+    double* mu = (double*)malloc((size_t)n * sizeof(double));
+    double* t1 = (double*)malloc((size_t)n * sizeof(double));
+    if (!cks || !seg || !q || !lam || !mu || !t1) {
+        free(cks); free(seg); free(q); free(lam); free(mu); free(t1);
+        return ORACLE_ENOMEM;
+    }
+    /* forward, keeping u at steps 0, K, 2K, ... */
+    memcpy(seg, u0, (size_t)n * sizeof(double));
+    for (int64_t m = 0; m < steps; ++m) {
+        if (m % K == 0) memcpy(cks + (m / K) * n, seg, (size_t)n * sizeof(double));
+        for (int64_t i = 0; i < n; ++i) q[i] = seg[i] + k.dth * ks_rhs_f64(seg, n, i, &k);
+        for (int64_t i = 0; i < n; ++i) t1[i] = seg[i] + k.dt * ks_rhs_f64(q, n, i, &k);
+        memcpy(seg, t1, (size_t)n * sizeof(double));
+    }
+    acc_t ja = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) {
+        double r = seg[i] - y[i];
+        lam[i] = r;
+        acc_add(&ja, 0.5 * r * r);
+    }
+    *J = acc_get(&ja);
+    /* reverse, segment by segment */
+    for (int64_t s0 = ((steps - 1) / K) * K; steps > 0 && s0 >= 0; s0 -= K) {
+        int64_t s1 = s0 + K < steps ? s0 + K : steps;
+        memcpy(seg, cks + (s0 / K) * n, (size_t)n * sizeof(double));
+        for (int64_t m = s0; m < s1 - 1; ++m) {
+            double* u = seg + (m - s0) * n;
+            for (int64_t i = 0; i < n; ++i) q[i] = u[i] + k.dth * ks_rhs_f64(u, n, i, &k);
+            for (int64_t i = 0; i < n; ++i) u[n + i] = u[i] + k.dt * ks_rhs_f64(q, n, i, &k);
+        }
+        for (int64_t m = s1 - 1; m >= s0; --m) {
+            double* u = seg + (m - s0) * n;
+            for (int64_t i = 0; i < n; ++i) q[i] = u[i] + k.dth * ks_rhs_f64(u, n, i, &k);
+            ks_jt_f64(q, lam, mu, n, &k);
+            for (int64_t i = 0; i < n; ++i) mu[i] = k.dt * mu[i];
+            ks_jt_f64(u, mu, t1, n, &k);
+            for (int64_t i = 0; i < n; ++i) lam[i] = (lam[i] + mu[i]) + k.dth * t1[i];
+        }
+    }
+    memcpy(g_u0, lam, (size_t)n * sizeof(double));
+    free(cks); free(seg); free(q); free(lam); free(mu); free(t1);
+    return ORACLE_OK;
+}
