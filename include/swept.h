@@ -234,7 +234,8 @@ typedef struct swept_batch_s* swept_batch;
  *                        formed as in swept_plan_create
  * The grids live back to back in one device array in input order (offsets
  * from swept_batch_info).  Every grid is run with the swept rule of
- * swept_run: wave-resident tiles of at most 1024 points with two halves of
+ * swept_run: wave-resident tiles of at most 64 P points (P = 8 points per
+ * lane for heat on the compacted engine, 16 otherwise) with two halves of
  * equal or neighbouring whole-lane widths (uneven tiles, flattened phases on
  * the wider halves), zig-zag tilings, edge bands through HBM (Sec. 4.2-4.3).
  * One persistent kernel runs the whole batch: each workgroup pulls the next

@@ -32,7 +32,6 @@
 namespace swept {
 namespace {
 
-constexpr int kBatchP = 16;  // points per lane
 constexpr int kBatchNW = 4;  // waves per workgroup
 
 template <typename T>
@@ -122,7 +121,12 @@ struct swept_batch_s {
   int64_t steps = 0;
   int64_t total_points = 0;
   std::vector<int64_t> offsets;  // per problem, input order
-  void* items = nullptr;         // device BatchItem<T>[nprob], queue order
+  // host copy of the problems, to rebuild the tiling when the engine changes
+  std::vector<int64_t> n;
+  std::vector<double> dt, dx, alpha;
+  std::vector<int32_t> order;  // queue order: largest first
+  int P = 16;                  // points per lane of the current tiling
+  void* items = nullptr;       // device BatchItem<T>[nprob], queue order
   void* slots = nullptr;
   size_t slots_bytes = 0;
   int* queue = nullptr;
@@ -137,43 +141,54 @@ struct swept_batch_s {
 
 namespace {
 
-bool compact_engine(const swept_batch_s* b) { return b->engine != SWEPT_ENGINE_WAVE; }
+bool compact_engine(int engine) { return engine != SWEPT_ENGINE_WAVE; }
 
-template <int KIND, typename T, int C>
+// Points per lane of the tiling an engine runs: the compacted heat tiles
+// take 8 (half the LDS and registers per wave, so three workgroups share a
+// CU), everything else 16 (measured best on MI355X for the 4096-grid
+// workloads: compacted heat 3.84e12 at 8 vs 3.17e12 at 16 cell-updates/s,
+// compacted KS 5.02e11 at 16 vs 4.75e11 at 8, register heat 3.02e12 at 16
+// vs 2.70e12 at 8).
+int points_per_lane(int kind, int engine) { return compact_engine(engine) && kind == SWEPT_HEAT_FTCS ? 8 : 16; }
+
+template <int KIND, typename T, int P, int C>
 void* batch_kernel_ptr() {
-  return reinterpret_cast<void*>(swept::batch_kernel<KIND, T, swept::kBatchP, swept::kBatchNW, C>);
+  return reinterpret_cast<void*>(swept::batch_kernel<KIND, T, P, swept::kBatchNW, C>);
 }
 
-template <int C>
-void* kernel_for_c(int kind, int dtype) {
+template <int P, int C>
+void* kernel_for_pc(int kind, int dtype) {
   if (kind == SWEPT_HEAT_FTCS)
-    return dtype == SWEPT_F64 ? batch_kernel_ptr<swept::kHeat, double, C>() : batch_kernel_ptr<swept::kHeat, float, C>();
-  return dtype == SWEPT_F64 ? batch_kernel_ptr<swept::kKS, double, C>() : batch_kernel_ptr<swept::kKS, float, C>();
+    return dtype == SWEPT_F64 ? batch_kernel_ptr<swept::kHeat, double, P, C>()
+                              : batch_kernel_ptr<swept::kHeat, float, P, C>();
+  return dtype == SWEPT_F64 ? batch_kernel_ptr<swept::kKS, double, P, C>() : batch_kernel_ptr<swept::kKS, float, P, C>();
 }
 
 void* kernel_for(const swept_batch_s* b) {
-  return compact_engine(b) ? kernel_for_c<1>(b->kind, b->dtype) : kernel_for_c<0>(b->kind, b->dtype);
+  const bool c = compact_engine(b->engine);
+  if (b->P == 8) return c ? kernel_for_pc<8, 1>(b->kind, b->dtype) : kernel_for_pc<8, 0>(b->kind, b->dtype);
+  return c ? kernel_for_pc<16, 1>(b->kind, b->dtype) : kernel_for_pc<16, 0>(b->kind, b->dtype);
 }
 
-template <int KIND, typename T, int C>
+template <int KIND, typename T, int P, int C>
 void launch_batch(const swept_batch_s* b, void* u, int64_t tiers, hipStream_t st) {
-  hipLaunchKernelGGL((swept::batch_kernel<KIND, T, swept::kBatchP, swept::kBatchNW, C>), dim3((unsigned)b->grid),
+  hipLaunchKernelGGL((swept::batch_kernel<KIND, T, P, swept::kBatchNW, C>), dim3((unsigned)b->grid),
                      dim3(64 * swept::kBatchNW), 0, st, static_cast<const BatchItem<T>*>(b->items), b->nprob,
                      static_cast<T*>(u), static_cast<T*>(b->slots), tiers, b->queue);
 }
 
-template <int C>
-void launch_batch_c(const swept_batch_s* b, void* u, int64_t tiers, hipStream_t st) {
+template <int P, int C>
+void launch_batch_pc(const swept_batch_s* b, void* u, int64_t tiers, hipStream_t st) {
   if (b->kind == SWEPT_HEAT_FTCS) {
     if (b->dtype == SWEPT_F64)
-      launch_batch<swept::kHeat, double, C>(b, u, tiers, st);
+      launch_batch<swept::kHeat, double, P, C>(b, u, tiers, st);
     else
-      launch_batch<swept::kHeat, float, C>(b, u, tiers, st);
+      launch_batch<swept::kHeat, float, P, C>(b, u, tiers, st);
   } else {
     if (b->dtype == SWEPT_F64)
-      launch_batch<swept::kKS, double, C>(b, u, tiers, st);
+      launch_batch<swept::kKS, double, P, C>(b, u, tiers, st);
     else
-      launch_batch<swept::kKS, float, C>(b, u, tiers, st);
+      launch_batch<swept::kKS, float, P, C>(b, u, tiers, st);
   }
 }
 
@@ -182,10 +197,18 @@ hipError_t enqueue_batch(swept_batch_s* b, void* u, hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tiers = b->steps * (b->kind == SWEPT_KS_RK2 ? 2 : 1);
-  if (compact_engine(b))
-    launch_batch_c<1>(b, u, tiers, st);
-  else
-    launch_batch_c<0>(b, u, tiers, st);
+  const bool c = compact_engine(b->engine);
+  if (b->P == 8) {
+    if (c)
+      launch_batch_pc<8, 1>(b, u, tiers, st);
+    else
+      launch_batch_pc<8, 0>(b, u, tiers, st);
+  } else {
+    if (c)
+      launch_batch_pc<16, 1>(b, u, tiers, st);
+    else
+      launch_batch_pc<16, 0>(b, u, tiers, st);
+  }
   return hipGetLastError();
 }
 
@@ -224,33 +247,71 @@ Consts<T> consts_for(double dt, double dx, double alpha) {
   return k;
 }
 
+// Grid descriptors of the tiling with P points per lane, in queue order.
 template <typename T>
-std::vector<BatchItem<T>> make_items(int kind, int32_t nprob, const int64_t* n, const double* dt, const double* dx,
-                                     const double* alpha, const std::vector<int32_t>& order,
-                                     const std::vector<int64_t>& offsets, size_t* slot_values) {
-  const int P = swept::kBatchP;
-  const int S = kind == SWEPT_KS_RK2 ? 2 : 1;
+std::vector<BatchItem<T>> make_items(const swept_batch_s* b, int P, size_t* slot_values) {
+  const int S = b->kind == SWEPT_KS_RK2 ? 2 : 1;
   const int64_t slen = 64 * P + 2 * S;
-  std::vector<BatchItem<T>> items((size_t)nprob);
+  std::vector<BatchItem<T>> items((size_t)b->nprob);
   int64_t soff = 0;
-  for (int32_t q = 0; q < nprob; ++q) {
-    const int32_t i = order[(size_t)q];
+  for (int32_t q = 0; q < b->nprob; ++q) {
+    const int32_t i = b->order[(size_t)q];
     BatchItem<T>& it = items[(size_t)q];
-    const int c = (int)(n[i] / P);
-    it.u_off = offsets[(size_t)i];
+    const int c = (int)(b->n[(size_t)i] / P);
+    it.u_off = b->offsets[(size_t)i];
     it.slot_off = soff;
-    it.n = (int32_t)n[i];
+    it.n = (int32_t)b->n[(size_t)i];
     it.nt = (c + 63) / 64;
     const int hb = c / (2 * it.nt);
     int h = hb * P / S;
-    if (kind == SWEPT_KS_RK2) h &= ~1;
+    if (b->kind == SWEPT_KS_RK2) h &= ~1;
     it.h = h;
     it.pad = 0;
-    it.k = consts_for<T>(dt[i], dx[i], kind == SWEPT_HEAT_FTCS ? alpha[i] : 0.0);
+    it.k = consts_for<T>(b->dt[(size_t)i], b->dx[(size_t)i], b->kind == SWEPT_HEAT_FTCS ? b->alpha[(size_t)i] : 0.0);
     soff += 2 * (int64_t)it.nt * slen;
   }
   *slot_values = (size_t)soff;
   return items;
+}
+
+// (Re)build the device descriptors and edge slots for P points per lane.
+// On failure the plan keeps its previous tiling.
+int build_tiling(swept_batch_s* b, int P) {
+  size_t slot_values = 0, item_bytes = 0;
+  const void* host_items = nullptr;
+  std::vector<BatchItem<double>> id;
+  std::vector<BatchItem<float>> ifl;
+  if (b->dtype == SWEPT_F64) {
+    id = make_items<double>(b, P, &slot_values);
+    host_items = id.data();
+    item_bytes = id.size() * sizeof(BatchItem<double>);
+  } else {
+    ifl = make_items<float>(b, P, &slot_values);
+    host_items = ifl.data();
+    item_bytes = ifl.size() * sizeof(BatchItem<float>);
+  }
+  const size_t es = b->dtype == SWEPT_F64 ? sizeof(double) : sizeof(float);
+  void* items = nullptr;
+  void* slots = nullptr;
+  hipError_t e = hipMalloc(&items, item_bytes);
+  if (e == hipSuccess) e = hipMalloc(&slots, slot_values * es);
+  if (e != hipSuccess) {
+    if (items) (void)hipFree(items);
+    return bfail(SWEPT_ENOMEM, std::string("hipMalloc(batch): ") + hipGetErrorString(e));
+  }
+  e = hipMemcpy(items, host_items, item_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(items);
+    (void)hipFree(slots);
+    return bhip(e, "hipMemcpy(batch items)");
+  }
+  if (b->items) (void)hipFree(b->items);
+  if (b->slots) (void)hipFree(b->slots);
+  b->items = items;
+  b->slots = slots;
+  b->slots_bytes = slot_values * es;
+  b->P = P;
+  return SWEPT_OK;
 }
 
 void batch_free(swept_batch_s* b) {
@@ -276,9 +337,8 @@ int swept_batch_create(swept_batch* out, int32_t nprob, const int64_t* n, int ki
   if (nprob < 1) return bfail(SWEPT_EINVAL, "nprob must be >= 1");
   if (!n || !dt || !dx || (kind == SWEPT_HEAT_FTCS && !alpha)) return bfail(SWEPT_EINVAL, "null host array");
   if (steps < 0) return bfail(SWEPT_EINVAL, "steps must be >= 0");
-  const int P = swept::kBatchP;
   for (int32_t i = 0; i < nprob; ++i) {
-    if (n[i] < 2 * P || n[i] % P != 0 || n[i] > (int64_t)1 << 30)
+    if (n[i] < 32 || n[i] % 16 != 0 || n[i] > (int64_t)1 << 30)
       return bfail(SWEPT_EUNSUPPORTED, "problem " + std::to_string(i) +
                                            ": n must be a multiple of 16, at least 32 and at most 2^30");
     if (!std::isfinite(dt[i]) || !std::isfinite(dx[i]) || dx[i] == 0.0 ||
@@ -291,6 +351,10 @@ int swept_batch_create(swept_batch* out, int32_t nprob, const int64_t* n, int ki
   b->dtype = dtype;
   b->nprob = nprob;
   b->steps = steps;
+  b->n.assign(n, n + nprob);
+  b->dt.assign(dt, dt + nprob);
+  b->dx.assign(dx, dx + nprob);
+  b->alpha = kind == SWEPT_HEAT_FTCS ? std::vector<double>(alpha, alpha + nprob) : std::vector<double>((size_t)nprob, 0.0);
   b->offsets.resize((size_t)nprob);
   int64_t off = 0;
   for (int32_t i = 0; i < nprob; ++i) {
@@ -299,40 +363,24 @@ int swept_batch_create(swept_batch* out, int32_t nprob, const int64_t* n, int ki
   }
   b->total_points = off;
   // queue order: largest first (ties by input index)
-  std::vector<int32_t> order((size_t)nprob);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return n[x] > n[y]; });
+  b->order.resize((size_t)nprob);
+  std::iota(b->order.begin(), b->order.end(), 0);
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int32_t x, int32_t y) { return n[x] > n[y]; });
 
   hipError_t e = hipGetDevice(&b->device);
   if (e != hipSuccess) {
     delete b;
     return bhip(e, "hipGetDevice");
   }
-  size_t slot_values = 0;
-  size_t item_bytes = 0;
-  const void* host_items = nullptr;
-  std::vector<BatchItem<double>> id;
-  std::vector<BatchItem<float>> ifl;
-  if (dtype == SWEPT_F64) {
-    id = make_items<double>(kind, nprob, n, dt, dx, alpha, order, b->offsets, &slot_values);
-    host_items = id.data();
-    item_bytes = id.size() * sizeof(BatchItem<double>);
-  } else {
-    ifl = make_items<float>(kind, nprob, n, dt, dx, alpha, order, b->offsets, &slot_values);
-    host_items = ifl.data();
-    item_bytes = ifl.size() * sizeof(BatchItem<float>);
-  }
-  const size_t es = dtype == SWEPT_F64 ? sizeof(double) : sizeof(float);
-  b->slots_bytes = slot_values * es;
-  if ((e = hipMalloc(&b->items, item_bytes)) != hipSuccess || (e = hipMalloc(&b->slots, b->slots_bytes)) != hipSuccess ||
-      (e = hipMalloc(reinterpret_cast<void**>(&b->queue), sizeof(int))) != hipSuccess) {
+  int rc = build_tiling(b, points_per_lane(kind, b->engine));
+  if (rc != SWEPT_OK) {
     batch_free(b);
-    return bfail(SWEPT_ENOMEM, std::string("hipMalloc(batch): ") + hipGetErrorString(e));
+    return rc;
   }
-  e = hipMemcpy(b->items, host_items, item_bytes, hipMemcpyHostToDevice);
+  e = hipMalloc(reinterpret_cast<void**>(&b->queue), sizeof(int));
   if (e != hipSuccess) {
     batch_free(b);
-    return bhip(e, "hipMemcpy(batch items)");
+    return bfail(SWEPT_ENOMEM, std::string("hipMalloc(batch queue): ") + hipGetErrorString(e));
   }
   e = size_grid(b);
   if (e != hipSuccess) {
@@ -353,16 +401,23 @@ int swept_batch_set_engine(swept_batch b, int engine) {
   hipError_t e = hipGetDevice(&prev);
   if (e == hipSuccess && prev != b->device) e = hipSetDevice(b->device);
   if (e != hipSuccess) return bhip(e, "hipSetDevice");
-  const int old = b->engine;
-  b->engine = engine;
-  e = size_grid(b);
-  if (prev != b->device) (void)hipSetDevice(prev);
-  if (e != hipSuccess) {
-    b->engine = old;
-    return bhip(e, "occupancy query");
+  const int old_engine = b->engine;
+  const int P = points_per_lane(b->kind, engine);
+  int rc = SWEPT_OK;
+  if (P != b->P) rc = build_tiling(b, P);  // the slots hold no state between runs
+  if (rc == SWEPT_OK) {
+    b->engine = engine;
+    e = size_grid(b);
+    if (e != hipSuccess) {
+      b->engine = old_engine;
+      rc = bhip(e, "occupancy query");
+      if (P != points_per_lane(b->kind, old_engine)) (void)build_tiling(b, points_per_lane(b->kind, old_engine));
+    } else {
+      drop_graph(b);
+    }
   }
-  drop_graph(b);
-  return SWEPT_OK;
+  if (prev != b->device) (void)hipSetDevice(prev);
+  return rc;
 }
 
 int swept_batch_run(swept_batch b, void* u, int use_graph, void* stream) {

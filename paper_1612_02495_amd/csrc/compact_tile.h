@@ -28,6 +28,17 @@
 namespace swept {
 namespace compact {
 
+// Ordering of LDS accesses inside one tile.  A tile belongs to one wave and
+// so do its LDS buffers; the LDS operations of one wave execute in order, so
+// a wavefront-scope fence, which keeps the compiler from moving LDS accesses
+// across it, is all a layout change needs.  (In the batched kernel several
+// waves of a workgroup change layout at different times, so a workgroup
+// barrier there could even pair up different layout changes.)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // LDS index with one spare value every 32, which spreads lane-strided
 // accesses over more banks.
 __host__ __device__ constexpr int pad(int i) { return i + (i >> 5); }
@@ -189,10 +200,10 @@ __device__ __forceinline__ void v_narrow(T* sb, T* stg, int hv, int& done, int l
       const T tip0[S] = {};
       v_run<KIND, T, R, false, INS>(A, Q, buf, done, tend, lane, tip0, tip0, k, ends_of<P, R>(bd, lane));
       done = tend;
-      __syncthreads();  // every lane has read its row before the row is rewritten
+      wave_sync();  // every lane has read its row before the row is rewritten
 #pragma unroll
       for (int r = 0; r < R; ++r) stg[pad(xl + r)] = A[r];
-      __syncthreads();
+      wave_sync();
     }
     v_narrow<KIND, T, P, R + Step<KIND>::value, INS>(sb, stg, hv, done, lane, k, bd);
   }
@@ -236,14 +247,14 @@ __device__ __forceinline__ void l_narrow(T* sb, T* stg, int hl, bool empty_top, 
           }
         }
       }
-      __syncthreads();  // all reads of this layout's rows precede the writes
+      wave_sync();  // all reads of this layout's rows precede the writes
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         sb[pad(2 * (xl + r + S))] = buf[r][0];
         sb[pad(2 * (xl + r + S) + 1)] = buf[r][1];
         if (done < hl) stg[pad(xl + r)] = A[r];
       }
-      __syncthreads();
+      wave_sync();
     }
     l_narrow<KIND, T, P, R - ST, INS>(sb, stg, hl, empty_top, done, lane, k, bd);
   }
@@ -257,7 +268,6 @@ template <int KIND, typename T, int P, int ROLE, bool INS = false>
 __device__ __forceinline__ void tile_phase(T* u, int64_t n, int64_t origin, T* sL, T* sR, int hv, int hl,
                                            const Consts<T>& k, int lane, T* sb, T* stg, const Bnd& bd = Bnd{}) {
   constexpr int S = Radius<KIND>::value;
-  constexpr int B = P / S;
   constexpr int W = 64 * P;
   constexpr int HALF = 32 * P;
   constexpr int ST = Step<KIND>::value;
@@ -297,7 +307,7 @@ __device__ __forceinline__ void tile_phase(T* u, int64_t n, int64_t origin, T* s
         }
       }
     }
-    __syncthreads();
+    wave_sync();
     int done = 0;
     v_narrow<KIND, T, P, ST, INS>(sb, stg, hv, done, lane, k, bd);
 #pragma unroll
@@ -323,7 +333,7 @@ __device__ __forceinline__ void tile_phase(T* u, int64_t n, int64_t origin, T* s
         if (x < HALF - S * hv || x >= HALF + S * hv) A[r] = wave::pick((hv & 1) != 0, buf[r][1], buf[r][0]);
       }
     }
-    __syncthreads();  // the V's reads of sb and stg precede the Lambda's writes
+    wave_sync();  // the V's reads of sb and stg precede the Lambda's writes
   }
 
   if constexpr (ROLE == 2) {
@@ -363,7 +373,7 @@ __device__ __forceinline__ void tile_phase(T* u, int64_t n, int64_t origin, T* s
       sb[pad(2 * (lane * P + r + S) + 1)] = buf[r][1];
       if (done < hl) stg[pad(lane * P + r)] = A[r];
     }
-    __syncthreads();
+    wave_sync();
     l_narrow<KIND, T, P, P - ST, INS>(sb, stg, hl, empty_top, done, lane, k, bd);
     // outgoing slots: producer left side p = x (x < HALF + S), right side
     // p = x - HALF + S (x >= HALF - S)
@@ -397,17 +407,6 @@ __device__ __forceinline__ void tile_phase(T* u, int64_t n, int64_t origin, T* s
 // then not a block boundary.  Layout points outside the tile are don't-care:
 // their LDS loads read zero and their stores are skipped.  The row passes
 // between the V and the Lambda part through the staging row.
-
-// Several waves of one workgroup run uneven tiles side by side, each with its
-// own LDS buffers and its own number of layout changes, so ordering inside a
-// tile is a wave-level matter: the LDS operations of one wave execute in
-// order, and a wavefront-scope fence keeps the compiler from moving LDS
-// accesses across a layout change.  (A workgroup barrier here could pair up
-// different layout changes of different waves.)
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
 
 struct GTile {
   int w;  // tile points

@@ -103,9 +103,12 @@ def test_batch_full_workload_sampled():
         assert np.array_equal(parts[i], v.cpu().numpy()), f"grid {i} (n={n[i]})"
 
 
-def test_batch_engines_agree_and_switch():
-    n, dt, dx, alpha, u0 = _batch_case("ks", torch.float64, 33, seed=9, m=20)
-    b = Batch(n, "ks", torch.float64, dt, dx, alpha, 33)
+@pytest.mark.parametrize("kind", ["heat", "ks"])
+def test_batch_engines_agree_and_switch(kind):
+    # heat: the compacted tiling has 8 points per lane and the register one
+    # 16, so every switch rebuilds the grid descriptors and edge slots
+    n, dt, dx, alpha, u0 = _batch_case(kind, torch.float64, 33, seed=9, m=20)
+    b = Batch(n, kind, torch.float64, dt, dx, alpha, 33)
     x = torch.tensor(np.concatenate(u0), device="cuda")
     y = x.clone()
     b.run(x)                      # default: compacted, graph
