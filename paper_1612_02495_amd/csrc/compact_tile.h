@@ -5,9 +5,8 @@
 // Lambda part shrinks back (Sec. 4.2), so a wave that always spans the whole
 // tile leaves about half of its lanes on don't-care points.  Here the part of
 // the tile that a run of tiers touches is laid out over all 64 lanes with R
-// contiguous points per lane, R = step, 2 step, .., P (step 2 for the 3-point
-// stencil, 4 for the 5-point one so that every layout holds whole KS step
-// pairs).  A layout R covers the 64 R points centred on the tile middle,
+// contiguous points per lane, R = 4, 8, .., P (see Step below).  A layout R
+// covers the 64 R points centred on the tile middle,
 // x in [32 (P - R), 32 (P + R)).  The V part starts in the narrowest layout
 // and widens as its gap grows, the Lambda part starts in the full layout and
 // narrows as its triangle climbs; each change of layout passes the live row
@@ -43,9 +42,15 @@ __device__ __forceinline__ void wave_sync() {
 // accesses over more banks.
 __host__ __device__ constexpr int pad(int i) { return i + (i >> 5); }
 
+// Layouts grow in steps of 4 points per lane for both stencils.  (The
+// 5-point stencil needs a multiple of 4 so that every layout holds whole KS
+// step pairs.  For heat, steps of 2 leave fewer idle lanes but pay twice the
+// layout changes and twice the unrolled code; on MI355X the heat FP64 N=2^20
+// diamond ran at 4.40e12 cell-updates/s with steps of 2, 4.44e12 with 4 and
+// 4.12e12 with 8, FP32 5.40e12 / 5.74e12 / 5.16e12.)
 template <int KIND>
 struct Step {
-  static constexpr int value = Radius<KIND>::value == 1 ? 2 : 4;
+  static constexpr int value = 4;
 };
 
 // LDS values of the band buffer and of the relayout staging row.
