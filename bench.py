@@ -10,7 +10,7 @@ throughput on the same workload, the roofline of the dominant kernel (the
 diamond phase) and the CPU oracle's throughput on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload heat|heat_f32|heat_rod|ks|batch|batch_ks|adjoint]
+                    [--workload heat|heat_f32|heat_rod|ks|batch|batch_ks|adjoint|ks_adjoint]
 """
 from __future__ import annotations
 
@@ -59,6 +59,10 @@ WORKLOADS = {
                     desc="gradient of J = 1/2 ||u_T - y||^2 w.r.t. u0 and alpha for 64 periodic heat "
                          "FTCS grids, N=2^18, FP64, 1e4 steps: checkpointed swept forward + swept "
                          "adjoint (one bench step = forward + reverse)"),
+    "ks_adjoint": dict(kind="ks", dtype="f64", n=2 ** 20, horizon=20000, tile=64, adjoint=1,
+                       desc="gradient of J = 1/2 ||u_T - y||^2 w.r.t. u0 for one periodic Kuramoto-"
+                            "Sivashinsky grid, N=2^20, FP64, dx=0.5, dt=0.005, 2e4 RK2 steps: checkpointed "
+                            "swept forward + swept adjoint (one bench step = forward + reverse)"),
 }
 
 
@@ -132,6 +136,89 @@ def run_adjoint(args, wl):
         el = _time.perf_counter() - t0
         cpu = {"value": n * cs / el, "unit": "cell-updates/s of gradient (forward + reverse)", "cores": 1,
                "kind": "oracle", "sample": f"one of the {B} grids, {cs} of the {T} steps, single-thread C "
+                                           f"checkpointed reverse sweep, {el:.1f} s"}
+    return {
+        "metric": METRIC, "value": updates / t, "unit": "cell-updates/s of gradient (forward + reverse)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded; see paper_1612_02495_amd/inputs.py)",
+        "config": {"workload": wl["desc"], "batch": B, "n": n, "timesteps": T,
+                   "adjoint_grad_ms": 1e3 * t / args.steps, "forward_ckpt_ms": 1e3 * t_fwd / args.steps,
+                   "checkpoint_bytes": plan.info["checkpoint_bytes"],
+                   "tile_width": plan.info["tile_width"], "steps_per_cycle": plan.info["steps_per_cycle"],
+                   "leading_classic_steps": plan.info["leading_classic_steps"], "parallelism": "single GPU"},
+        "roofline": roof, "naive": None, "speedup_vs_naive": None, "cpu_baseline": cpu,
+    }
+
+
+def run_ks_adjoint(args, wl):
+    """KS adjoint workload: one bench step = swept_ks_forward_ckpt + swept_ks_adjoint_run."""
+    import torch
+
+    from paper_1612_02495_amd import KsAdjointPlan, inputs
+    B = args.batch or wl["adjoint"]
+    T = wl["horizon"]
+    u0, u0t, dt, dx, _ = inputs.ks_adjoint(batch=B, n=wl["n"], steps=T)
+    n = u0.shape[1]
+    plan = KsAdjointPlan(B, n, dt, dx, T)
+    du0 = torch.tensor(u0, device="cuda")
+    # the target: a forward run from the perturbed initial states
+    y = torch.empty_like(du0)
+    plan.forward(torch.tensor(u0t, device="cuda"), y)
+    uT = torch.empty_like(du0)
+    g_u0 = torch.empty_like(du0)
+
+    def step():
+        plan.forward(du0, uT)
+        plan.adjoint((uT - y).contiguous(), g_u0)
+
+    for _ in range(args.warmup):
+        step()
+    t = _time_runs(step, args.steps, torch)
+    t_fwd = _time_runs(lambda: plan.forward(du0, uT), args.steps, torch)
+    updates = B * n * T * args.steps
+
+    # Dominant kernel: the fused reverse region launch.  Its time per launch is
+    # the difference of two reverse sweeps whose horizons differ by D full
+    # phases (same remainder), timed with events on the launch stream.
+    # Algorithmic flops per launch: every tile's region holds w h = 1024
+    # sub-step updates, each recomputed (20 flops) and walked back by the
+    # adjoint: Jf^T w costs 13 (2 for the nonlinear weight, 2 for the two
+    # neighbour weights, 5 products and 4 sums), plus 1 (dt mu, odd tiers) or 3
+    # ((lambda'' + mu) + dt/2 Jf^T mu, even tiers): 35 per update on average.
+    roof = None
+    if not args.no_dominant:
+        h = plan.info["steps_per_cycle"]
+        r = plan.info["leading_classic_steps"]
+        k_lo, k_hi = 8, 40
+        times = {}
+        for kk in (k_lo, k_hi):
+            pk = KsAdjointPlan(B, n, dt, dx, kk * h + r)
+            uk = torch.empty_like(du0)
+            pk.forward(du0, uk)
+            gk = (uk - y).contiguous()
+            pk.adjoint(gk, g_u0)  # warm-up
+            times[kk] = _time_runs(lambda: pk.adjoint(gk, g_u0), 3, torch) / 3
+            pk.close()
+            del uk, gk
+        t_launch = (times[k_hi] - times[k_lo]) / (k_hi - k_lo)
+        w = plan.info["tile_width"]
+        tiers = 2 * h
+        flops = B * (n // w) * w * tiers * (20 + 15)
+        achieved = flops / t_launch / 1e12
+        roof = {"bound": "alu", "kernel": "fused reverse region launch (recompute + adjoint walk)",
+                "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS,
+                "traffic": None, "launch_ms": 1e3 * t_launch, "flops_per_launch": flops}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import time as _time
+        import oracle
+        cs = args.cpu_steps or 120
+        t0 = _time.perf_counter()
+        oracle.ks_adjoint(u0[0], u0t[0], dt, dx, cs)
+        el = _time.perf_counter() - t0
+        cpu = {"value": n * cs / el, "unit": "cell-updates/s of gradient (forward + reverse)", "cores": 1,
+               "kind": "oracle", "sample": f"grid 0 of {B}, {cs} of the {T} steps, single-thread C "
                                            f"checkpointed reverse sweep, {el:.1f} s"}
     return {
         "metric": METRIC, "value": updates / t, "unit": "cell-updates/s of gradient (forward + reverse)",
@@ -301,7 +388,7 @@ def main(argv=None):
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle timesteps in the CPU sample")
     ap.add_argument("--no-dominant", action="store_true",
                     help="skip the per-launch timing of the diamond kernel (short profiler passes)")
-    ap.add_argument("--batch", type=int, default=0, help="grids in the adjoint workload (0 = 64)")
+    ap.add_argument("--batch", type=int, default=0, help="grids in the adjoint workloads (0 = 64 heat, 1 KS)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args(argv)
@@ -322,7 +409,7 @@ def main(argv=None):
         print(json.dumps(run_batch(args, wl)))
         return 0
     if wl.get("adjoint"):
-        print(json.dumps(run_adjoint(args, wl)))
+        print(json.dumps(run_ks_adjoint(args, wl) if wl["kind"] == "ks" else run_adjoint(args, wl)))
         return 0
     tile = args.tile or wl["tile"]
     p = _problem(wl)

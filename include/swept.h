@@ -332,6 +332,60 @@ int swept_adjoint_info(swept_adjoint a, size_t* checkpoint_bytes, int* tile_widt
 /* swept_adjoint_destroy -- free the plan and its workspace (NULL is a no-op). */
 void swept_adjoint_destroy(swept_adjoint a);
 
+/* ----------------------------------------------------------- KS adjoint -- */
+
+typedef struct swept_ks_adjoint_s* swept_ks_adjoint;
+
+/*
+ * swept_ks_adjoint_create -- plan dJ/du_0 for a functional J of u_T, for a
+ * batch of `batch` periodic Kuramoto-Sivashinsky grids of n points each,
+ * advanced with the RK2 midpoint scheme of Sec. 4.1 (Eq. KSDisc, Appendix):
+ * q = u + (dt/2) f(u), u' = u + dt f(q), f the 5-point right-hand side, with
+ * the constants of swept_plan_create for SWEPT_KS_RK2.  All grids share dt,
+ * dx and the number of steps.
+ *   dtype  SWEPT_F64 (other types fail with EUNSUPPORTED)
+ *   n      a positive multiple of 64
+ *   steps  >= 1
+ * The forward pass runs swept phases of 8 steps (16 sub-step tiers) on tiles
+ * of 64 points and keeps the edge bands every phase writes as checkpoints;
+ * the first steps mod 8 run with the classic scheme and keep their grids.
+ * Workspace: about 2.1 n x 8 bytes per grid per phase of checkpoints,
+ * (steps mod 8 + 1) grids per grid of classic states, plus O(n) buffers --
+ * all owned by the plan (swept_ks_adjoint_info reports the checkpoint size).
+ * Errors: EINVAL, EUNSUPPORTED, ENOMEM.
+ */
+int swept_ks_adjoint_create(swept_ks_adjoint* out, int32_t batch, int64_t n, int dtype, double dt, double dx,
+                            int64_t steps);
+
+/*
+ * swept_ks_forward_ckpt -- u_T for every grid, storing the checkpoints the
+ * reverse sweep restarts from.  u0, uT: device, batch x n doubles,
+ * row-major (grid b at b*n), may not alias.  Asynchronous on `stream`.  The
+ * result equals swept_run / naive_run of each grid bit for bit.
+ */
+int swept_ks_forward_ckpt(swept_ks_adjoint a, const void* u0, void* uT, void* stream);
+
+/*
+ * swept_ks_adjoint_run -- reverse sweep after swept_ks_forward_ckpt: given
+ * g_uT = dJ/du_T (device, batch x n), writes g_u0 = dJ/du_0 (device,
+ * batch x n; may not alias g_uT).  For J = 1/2 ||u_T - y||^2, g_uT = u_T - y.
+ * Each step is reversed as mu = dt Jf(q)^T lambda',
+ * lambda = (lambda' + mu) + (dt/2) Jf(u)^T mu, with q and u recomputed
+ * phase by phase from the checkpoints; every swept phase, last to first, is
+ * one launch that recomputes its tiles in registers and walks the adjoint
+ * back through them.  Deterministic (no atomics, a fixed operation order).
+ * Asynchronous on `stream`.  EINVAL if no forward pass ran on this plan.
+ */
+int swept_ks_adjoint_run(swept_ks_adjoint a, const void* g_uT, void* g_u0, void* stream);
+
+/* swept_ks_adjoint_info -- checkpoint bytes, tile width (64), steps per
+ * cycle (8) and the number of leading classic steps (steps mod 8). */
+int swept_ks_adjoint_info(swept_ks_adjoint a, size_t* checkpoint_bytes, int* tile_width, int* steps_per_cycle,
+                          int64_t* leading_classic_steps);
+
+/* swept_ks_adjoint_destroy -- free the plan and its workspace (NULL is a no-op). */
+void swept_ks_adjoint_destroy(swept_ks_adjoint a);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,7 +10,9 @@ from .swept import (Plan, SweptError, naive_run, swept_last_error, swept_plan_cr
                     swept_autotune_forget, Batch, swept_batch_create, swept_batch_run, swept_batch_set_engine,
                     swept_batch_info,
                     swept_batch_destroy, AdjointPlan, swept_heat, swept_adjoint_create, swept_forward_ckpt,
-                    swept_adjoint_run, swept_adjoint_info, swept_adjoint_destroy)
+                    swept_adjoint_run, swept_adjoint_info, swept_adjoint_destroy, KsAdjointPlan, swept_ks,
+                    swept_ks_adjoint_create, swept_ks_forward_ckpt, swept_ks_adjoint_run, swept_ks_adjoint_info,
+                    swept_ks_adjoint_destroy)
 
 __all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
            "swept_plan_set_engine", "swept_plan_destroy", "swept_last_error", "swept_schedule",
@@ -18,4 +20,6 @@ __all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "naive_run", 
            "Batch", "swept_batch_create", "swept_batch_run", "swept_batch_set_engine", "swept_batch_info",
            "swept_batch_destroy",
            "AdjointPlan", "swept_heat", "swept_adjoint_create", "swept_forward_ckpt", "swept_adjoint_run",
-           "swept_adjoint_info", "swept_adjoint_destroy"]
+           "swept_adjoint_info", "swept_adjoint_destroy", "KsAdjointPlan", "swept_ks",
+           "swept_ks_adjoint_create", "swept_ks_forward_ckpt", "swept_ks_adjoint_run", "swept_ks_adjoint_info",
+           "swept_ks_adjoint_destroy"]

@@ -34,7 +34,8 @@ FLAGS = [
     f"-I{CSRC}",
 ]
 
-SOURCES = ["plan.hip", "naive.hip", "phase_lds.hip", "phase_wave.hip", "phase_compact.hip", "autotune.hip", "batch.hip", "adjoint.hip"]
+SOURCES = ["plan.hip", "naive.hip", "phase_lds.hip", "phase_wave.hip", "phase_compact.hip", "autotune.hip", "batch.hip", "adjoint.hip",
+           "adjoint_ks.hip"]
 
 
 def _compile(src: str) -> str:

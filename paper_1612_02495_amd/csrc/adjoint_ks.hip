@@ -1,0 +1,511 @@
+// Swept adjoint of the periodic Kuramoto-Sivashinsky RK2 scheme: dJ/du_0
+// for J a functional of u_T, for every grid of a batch, by a reverse swept
+// sweep that recomputes each swept cycle from its checkpointed edge states.
+//
+// Scheme (Eq. KSDisc with the RK2 midpoint of Sec. 4.1 and the Appendix):
+// q = u + (dt/2) f(u), u' = u + dt f(q), f the 5-point right-hand side.
+// Reverse mode, from lambda' = dJ/du':
+//   mu     = dt Jf(q)^T lambda'                  (dJ/dq)
+//   lambda = (lambda' + mu) + (dt/2) Jf(u)^T mu   (dJ/du)
+// Jf(v)^T w at point i only needs v_i and w at i-2 .. i+2:
+//   (2 v_i / (4 dx)) (w_{i-1} - w_{i+1}) + (w_{i-1} + w_{i+1} - 2 w_i)/dx^2
+//   + (w_{i-2} - 4 w_{i-1} + 6 w_i - 4 w_{i+1} + w_{i+2})/dx^4, negated,
+// evaluated with per-neighbour coefficients in the fixed order w_{i-1},
+// w_{i+1}, w_i, w_{i-2}, w_{i+2}, no contraction.
+//
+// In tier terms (tier 2m = u after m steps, tier 2m+1 = predictor) the
+// adjoint at tier d needs the adjoint at tier d+1 within two points and, for
+// even d, its own point at tier d+2: the transpose of the forward tier rule
+// (Sec. 4.3), with time reversed.  So the reverse sweep walks each swept
+// region top-down over the same tiles, with the same edge bands moving the
+// other way.
+//
+// Tiling.  Tiles of w = 64 points, one point per lane of one wave64, full
+// (pure) phases of h = w/4 = 16 tiers (8 steps); the T mod 8 leading steps
+// run with the classic scheme and keep their states.  Forward: phase p
+// writes its edge bands (the 4 outermost points per side and tier) into
+// checkpoint p.  Reverse, for p = K .. 0, one launch per phase: every tile
+//   1. recomputes its region (V then Lambda) from checkpoint p-1, keeping
+//      every tier of its own point in the lane's registers;
+//   2. walks the adjoint down the region: its Lambda part first, taking the
+//      adjoint of later regions just outside each tier from lambda slots,
+//      then its V part, handing the 4 outermost values of each gap tier per
+//      side on to the previous phase through the same slots.
+// Slots are position-major [p][t & 1] with (w/2 + 2) positions per side, as
+// in the forward engines: consumer left p = x + 2, right p = x - a; producer
+// left p = x (x < a + 2), right p = x - a + 2 (x >= a - 2).
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "internal.h"
+#include "swept.h"
+#include "wave_tile.h"
+
+namespace swept {
+namespace ksadj {
+
+constexpr int kW = 64;
+constexpr int kS = 2;
+constexpr int kH = kW / (2 * kS);  // 16 tiers (8 steps) per full triangle
+constexpr int kA = kW / 2;         // inner seam
+constexpr int kSL = kW + 2 * kS;
+constexpr int kThreads = 256;
+
+// Coefficients of Jf(v)^T, formed on the host in FP64.
+struct JtCoef {
+  double i4dx;  // 1/(4 dx)
+  double c1;    // idx2 - 4 idx4: the linear part of the w_{i-1}, w_{i+1} weights
+  double c0;    // -(6 idx4 - 2 idx2): weight of w_i
+  double c2;    // -idx4: weight of w_{i-2}, w_{i+2}
+};
+
+// (Jf(v)^T w)_i from v_i and w at i-2 .. i+2.
+__device__ __forceinline__ double jt(double v, double wl2, double wl1, double w, double wr1, double wr2,
+                                     const JtCoef& c) {
+  const double s = (2.0 * v) * c.i4dx;
+  const double dm = -(s + c.c1);  // d f_{i-1} / d v_i
+  const double dp = -(c.c1 - s);  // d f_{i+1} / d v_i
+  return (((dm * wl1 + dp * wr1) + c.c0 * w) + c.c2 * wl2) + c.c2 * wr2;
+}
+
+__device__ __forceinline__ bool in_range(int x, int lo, int hi) { return x >= lo && x < hi; }
+
+// The values two and one lanes to the left and right (zero past the wave).
+struct Nb {
+  double l2, l1, r1, r2;
+};
+
+__device__ __forceinline__ Nb nbrs(double v) {
+  using wave::dpp_move0;
+  Nb b;
+  b.l1 = dpp_move0<wave::kDppWaveShr1>(v);
+  b.r1 = dpp_move0<wave::kDppWaveShl1>(v);
+  b.l2 = dpp_move0<wave::kDppWaveShr1>(b.l1);
+  b.r2 = dpp_move0<wave::kDppWaveShl1>(b.r1);
+  return b;
+}
+
+// Points -2, -1 and w, w+1 of a row that reaches past the tile.
+__device__ __forceinline__ void fix_ends(Nb& b, int x, double tl0, double tl1, double tr0, double tr1) {
+  using wave::pick;
+  b.l1 = pick(x == 0, tl1, b.l1);
+  b.l2 = pick(x == 0, tl0, pick(x == 1, tl1, b.l2));
+  b.r1 = pick(x == kW - 1, tr0, b.r1);
+  b.r2 = pick(x == kW - 1, tr1, pick(x == kW - 2, tr0, b.r2));
+}
+
+// Positions just outside Lambda tier t of a tile whose adjoint belongs to
+// later regions: [2t - 4, 2t) and [w - 2t, w - 2t + 4).
+__device__ __forceinline__ bool outside(int x, int t) {
+  return in_range(x, kS * t - 2 * kS, kS * t) || in_range(x, kW - kS * t, kW - kS * t + 2 * kS);
+}
+
+// One swept region of one tile in one wave64 (lane x = tile point x).
+// MODE 0: forward phase writing checkpoint slots (or u_T).  MODE 1: fused
+// adjoint (recompute, then the adjoint walk).  HV: the region has a V part
+// (every phase but the first); HL: it has a Lambda part (every phase but the
+// last).
+template <int MODE, bool HV, bool HL>
+__global__ void __launch_bounds__(kW)
+region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const double* __restrict__ ck_in,
+              double* __restrict__ ck_out, const double* __restrict__ gT, double* lam_slots,
+              double* __restrict__ g_ur, Consts<double> k, JtCoef c, int64_t n, int64_t nt, int p) {
+  using wave::pick;
+  const int x = threadIdx.x;
+  const int64_t b = blockIdx.x / nt;
+  const int64_t j = blockIdx.x % nt;
+  const int par = p & 1;
+  const int64_t origin = j * kW + (par ? kA : 0);
+  const int64_t base = b * 2 * nt * kSL;
+  const int64_t sL = base + (par ? (nt + j) * kSL : j * kSL);
+  const int64_t sR = base + (par ? ((j + 1) % nt) * kSL : (nt + j) * kSL);
+  int64_t gx = origin + x;
+  if (gx >= n) gx -= n;
+  const int64_t gidx = b * n + gx;
+  // this lane's entry in the incoming slots (one value per tier parity)
+  const int64_t src = x < kA ? sL + 2 * (x + kS) : sR + 2 * (x - kA);
+
+  // ------------------------------------------------ forward recompute --
+  double hist[2 * kH];  // u or q at (x, d), d = 0 .. 2h-1 (MODE 0 keeps only live tiers)
+  if constexpr (!HV) {
+    hist[kH] = ustart[gidx];
+  } else {
+    const double bv0 = ck_in[src], bv1 = ck_in[src + 1];
+    // band points -2, -1, w, w+1 of tier h-1
+    constexpr int tp = (kH - 1) & 1;
+    const double tl0 = ck_in[sL + tp], tl1 = ck_in[sL + 2 + tp];
+    const double tr0 = ck_in[sR + 2 * kA + tp], tr1 = ck_in[sR + 2 * (kA + 1) + tp];
+    double row = 0.0;
+#pragma unroll
+    for (int t = 0; t < kH; ++t) {
+      // bands of tier t: [a-4-2t, a-2t) and [a+2t, a+2t+4)
+      const bool band = in_range(x, kA - 2 * kS - kS * t, kA - kS * t) || in_range(x, kA + kS * t, kA + kS * t + 2 * kS);
+      row = pick(band, (t & 1) ? bv1 : bv0, row);
+      hist[t] = row;
+      Nb nb = nbrs(row);
+      if (t == kH - 1) fix_ends(nb, x, tl0, tl1, tr0, tr1);
+      if ((t + 1) & 1)
+        row = ks_predictor(nb.l2, nb.l1, row, nb.r1, nb.r2, k);
+      else
+        row = ks_final(hist[t > 0 ? t - 1 : 0], nb.l2, nb.l1, row, nb.r1, nb.r2, k);
+    }
+    hist[kH] = row;
+  }
+  if constexpr (HL) {
+    double row = hist[kH];
+    double o0 = 0.0, o1 = 0.0;  // MODE 0: this lane's outgoing band values
+#pragma unroll
+    for (int m = 0; m < kH; ++m) {
+      if (m > 0) {
+        const Nb nb = nbrs(row);
+        if ((kH + m) & 1)
+          row = ks_predictor(nb.l2, nb.l1, row, nb.r1, nb.r2, k);
+        else
+          row = ks_final(hist[kH + m - 2], nb.l2, nb.l1, row, nb.r1, nb.r2, k);
+        hist[kH + m] = row;
+      }
+      if constexpr (MODE == 0) {
+        // bands of Lambda tier m: [2m, 2m+4) and [w-2m-4, w-2m)
+        const bool band = in_range(x, kS * m, kS * m + 2 * kS) || in_range(x, kW - kS * m - 2 * kS, kW - kS * m);
+        if (m & 1)
+          o1 = pick(band, row, o1);
+        else
+          o0 = pick(band, row, o0);
+      }
+    }
+    if constexpr (MODE == 0) {
+      // left side p = x (x < a+2) at tiers m = x/2 - 1, x/2; right side
+      // p = x - a + 2 (x >= a-2) at tiers m = ceil((w-4-x)/2) + 0, 1
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int ml = x / kS - 1 + e;
+        if (x < kA + kS && ml >= 0 && ml <= kH - 1) ck_out[sL + 2 * x + (ml & 1)] = (ml & 1) ? o1 : o0;
+        const int mr = (kW - x + 1) / kS - 2 + e;
+        if (x >= kA - kS && mr >= 0 && mr <= kH - 1)
+          ck_out[sR + 2 * (x - kA + kS) + (mr & 1)] = (mr & 1) ? o1 : o0;
+      }
+    }
+  } else if constexpr (MODE == 0) {
+    uT[gidx] = hist[kH];
+  }
+  if constexpr (MODE == 1) {
+    // --------------------------------------------------- adjoint sweep --
+    double in0 = 0.0, in1 = 0.0, ll0 = 0.0, ll1 = 0.0, lr0 = 0.0, lr1 = 0.0;
+    if constexpr (HL) {
+      in0 = lam_slots[src];
+      in1 = lam_slots[src + 1];
+      // adjoint of points -2, -1, w, w+1 at tier h+1
+      ll0 = lam_slots[sL + 1];
+      ll1 = lam_slots[sL + 3];
+      lr0 = lam_slots[sR + 2 * kA + 1];
+      lr1 = lam_slots[sR + 2 * (kA + 1) + 1];
+    }
+    double lam = 0.0, lam2 = 0.0;  // adjoint at tiers d+1 and d+2
+    if constexpr (HL)
+      lam = pick(outside(x, kH), (kH & 1) ? in1 : in0, lam);
+    else
+      lam = gT[gidx];  // the region's top tier h is u_T
+    double oL0 = 0.0, oL1 = 0.0, oR0 = 0.0, oR1 = 0.0;
+#pragma unroll
+    for (int d = HL ? 2 * kH - 1 : kH; d >= (HV ? 1 : kH); --d) {
+      if (HL || d < kH) {
+        Nb nb = nbrs(lam);
+        if (HL && d == kH) fix_ends(nb, x, ll0, ll1, lr0, lr1);
+        const double g = jt(hist[d], nb.l2, nb.l1, lam, nb.r1, nb.r2, c);
+        const double nw = (d & 1) ? k.dt * g : (lam2 + lam) + k.dth * g;
+        lam2 = lam;
+        lam = nw;
+        if (HL && d > kH) {
+          const int t = d - kH;
+          lam = pick(outside(x, t), (t & 1) ? in1 : in0, lam);
+        }
+      }
+      if (HV && d <= kH) {
+        // the 4 outermost values on each side of gap(d) go to the previous phase
+        const bool ol = in_range(x, kA - kS * d, kA - kS * d + 2 * kS);
+        const bool orr = in_range(x, kA + kS * d - 2 * kS, kA + kS * d);
+        if (d & 1) {
+          oL1 = pick(ol, lam, oL1);
+          oR1 = pick(orr, lam, oR1);
+        } else {
+          oL0 = pick(ol, lam, oL0);
+          oR0 = pick(orr, lam, oR0);
+        }
+      }
+      if (!HV && d == kH) g_ur[gidx] = lam;
+    }
+    if constexpr (HV) {
+      // left: lanes x < a+2 at d = ceil((a-x)/2) + 0, 1; right: lanes
+      // x >= a-2 at d = floor((x-a)/2) + 1, 2 (d in [1, h])
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int dl = (kA - x + 1) / 2 + e;
+        if (x < kA + kS && dl >= 1 && dl <= kH) lam_slots[sL + 2 * x + (dl & 1)] = (dl & 1) ? oL1 : oL0;
+        const int dr = (x - kA + 2) / 2 + e;
+        if (x >= kA - kS && dr >= 1 && dr <= kH)
+          lam_slots[sR + 2 * (x - kA + kS) + (dr & 1)] = (dr & 1) ? oR1 : oR0;
+      }
+    }
+  }
+}
+
+// Periodic neighbour of x at offset o (|o| <= 2 < n).
+__device__ __forceinline__ int64_t wrap(int64_t x, int o, int64_t n) {
+  int64_t y = x + o;
+  if (y < 0) y += n;
+  if (y >= n) y -= n;
+  return y;
+}
+
+__device__ __forceinline__ double rhs_at(const double* v, int64_t x, int64_t n, const Consts<double>& k) {
+  return ks_rhs(v[wrap(x, -2, n)], v[wrap(x, -1, n)], v[x], v[wrap(x, 1, n)], v[wrap(x, 2, n)], k);
+}
+
+// Leading classic steps, forward: q = u + (dt/2) f(u) ...
+__global__ void __launch_bounds__(kThreads)
+rem_pred_kernel(const double* __restrict__ u, double* __restrict__ q, Consts<double> k, int64_t n, int64_t total) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= total) return;
+  const double* v = u + (i / n) * n;
+  const int64_t x = i % n;
+  q[i] = v[x] + k.dth * rhs_at(v, x, n, k);
+}
+
+// ... then u' = u + dt f(q), out of place.
+__global__ void __launch_bounds__(kThreads)
+rem_final_kernel(const double* __restrict__ u, const double* __restrict__ q, double* __restrict__ un,
+                 Consts<double> k, int64_t n, int64_t total) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= total) return;
+  const double* w = q + (i / n) * n;
+  const int64_t x = i % n;
+  un[i] = u[i] + k.dt * rhs_at(w, x, n, k);
+}
+
+// Leading classic steps, reverse: mu = dt Jf(q)^T lambda', with q at the
+// own point recomputed from u ...
+__global__ void __launch_bounds__(kThreads)
+rem_mu_kernel(const double* __restrict__ u, const double* __restrict__ lin, double* __restrict__ mu,
+              Consts<double> k, JtCoef c, int64_t n, int64_t total) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= total) return;
+  const int64_t row = (i / n) * n;
+  const int64_t x = i % n;
+  const double* v = u + row;
+  const double* l = lin + row;
+  const double q = v[x] + k.dth * rhs_at(v, x, n, k);
+  mu[i] = k.dt * jt(q, l[wrap(x, -2, n)], l[wrap(x, -1, n)], l[x], l[wrap(x, 1, n)], l[wrap(x, 2, n)], c);
+}
+
+// ... then lambda = (lambda' + mu) + (dt/2) Jf(u)^T mu.
+__global__ void __launch_bounds__(kThreads)
+rem_lam_kernel(const double* __restrict__ u, const double* __restrict__ lin, const double* __restrict__ mu,
+               double* __restrict__ lout, Consts<double> k, JtCoef c, int64_t n, int64_t total) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= total) return;
+  const int64_t row = (i / n) * n;
+  const int64_t x = i % n;
+  const double* m = mu + row;
+  const double g = jt(u[i], m[wrap(x, -2, n)], m[wrap(x, -1, n)], m[x], m[wrap(x, 1, n)], m[wrap(x, 2, n)], c);
+  lout[i] = (lin[i] + mu[i]) + k.dth * g;
+}
+
+}  // namespace ksadj
+}  // namespace swept
+
+struct swept_ks_adjoint_s {
+  int32_t batch = 0;
+  int64_t n = 0, steps = 0, nt = 0;
+  int K = 0;  // full phases of 8 steps; phases 0..K
+  int r = 0;  // leading classic steps
+  swept::Consts<double> k{};
+  swept::ksadj::JtCoef c{};
+  bool have_forward = false;
+  double* ckpt = nullptr;       // K phases x batch x 2nt x 68
+  double* lam_slots = nullptr;  // batch x 2nt x 68
+  double* rem = nullptr;        // (r+1) states x batch x n: u_0 .. u_r
+  double* tmp = nullptr;        // batch x n: predictor / mu
+  double* lam_a = nullptr;      // batch x n
+  double* lam_b = nullptr;
+  size_t ckpt_bytes = 0;
+};
+
+namespace {
+
+using swept::ksadj::kSL;
+using swept::ksadj::kThreads;
+using swept::ksadj::kW;
+
+int kfail(int code, const std::string& m) { return swept::set_error(code, m); }
+int khip(hipError_t e, const char* what) {
+  return kfail(SWEPT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void ks_free(swept_ks_adjoint_s* a) {
+  for (double* q : {a->ckpt, a->lam_slots, a->rem, a->tmp, a->lam_a, a->lam_b})
+    if (q) (void)hipFree(q);
+  delete a;
+}
+
+dim3 grid_for(int64_t total) { return dim3((unsigned)((total + kThreads - 1) / kThreads)); }
+
+}  // namespace
+
+extern "C" {
+
+int swept_ks_adjoint_create(swept_ks_adjoint* out, int32_t batch, int64_t n, int dtype, double dt, double dx,
+                            int64_t steps) {
+  if (!out) return kfail(SWEPT_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (batch < 1) return kfail(SWEPT_EINVAL, "batch must be >= 1");
+  if (dtype != SWEPT_F64) return kfail(SWEPT_EUNSUPPORTED, "the KS adjoint is built for SWEPT_F64");
+  if (n < kW || n % kW != 0) return kfail(SWEPT_EUNSUPPORTED, "n must be a positive multiple of 64");
+  if (steps < 1) return kfail(SWEPT_EINVAL, "steps must be >= 1");
+  if (!std::isfinite(dt) || !std::isfinite(dx) || dx == 0.0)
+    return kfail(SWEPT_EINVAL, "dt, dx must be finite, dx != 0");
+  const int64_t total = (int64_t)batch * n;
+  if ((total + kThreads - 1) / kThreads > 0x7fffffff || (int64_t)batch * (n / kW) > 0x7fffffff)
+    return kfail(SWEPT_EINVAL, "batch x n too large for one launch");
+  auto* a = new (std::nothrow) swept_ks_adjoint_s();
+  if (!a) return kfail(SWEPT_ENOMEM, "host allocation failed");
+  a->batch = batch;
+  a->n = n;
+  a->steps = steps;
+  a->nt = n / kW;
+  constexpr int spp = swept::ksadj::kH / 2;
+  a->r = (int)(steps % spp);
+  a->K = (int)(steps / spp);
+  // same formulas as swept_plan_create for SWEPT_KS_RK2 (Sec. 4.1, Sec. 5)
+  a->k.i4dx = 1.0 / (4.0 * dx);
+  a->k.idx2 = 1.0 / (dx * dx);
+  a->k.idx4 = a->k.idx2 * a->k.idx2;
+  a->k.dt = dt;
+  a->k.dth = 0.5 * dt;
+  a->c.i4dx = a->k.i4dx;
+  a->c.c1 = a->k.idx2 - 4.0 * a->k.idx4;
+  a->c.c0 = -(6.0 * a->k.idx4 - 2.0 * a->k.idx2);
+  a->c.c2 = -a->k.idx4;
+  const size_t state = (size_t)total * sizeof(double);
+  const size_t slots = (size_t)batch * 2 * (size_t)a->nt * kSL * sizeof(double);
+  a->ckpt_bytes = (size_t)a->K * slots;
+  struct Alloc {
+    double** p;
+    size_t bytes;
+  } allocs[] = {
+      {&a->ckpt, std::max<size_t>(a->ckpt_bytes, 8)},
+      {&a->lam_slots, slots},
+      {&a->rem, (size_t)(a->r + 1) * state},
+      {&a->tmp, state},
+      {&a->lam_a, state},
+      {&a->lam_b, state},
+  };
+  for (const Alloc& al : allocs) {
+    const hipError_t e = hipMalloc(reinterpret_cast<void**>(al.p), al.bytes);
+    if (e != hipSuccess) {
+      ks_free(a);
+      return kfail(SWEPT_ENOMEM, std::string("hipMalloc(KS adjoint workspace): ") + hipGetErrorString(e));
+    }
+  }
+  *out = a;
+  return SWEPT_OK;
+}
+
+int swept_ks_forward_ckpt(swept_ks_adjoint a, const void* u0, void* uT, void* stream) {
+  if (!a) return kfail(SWEPT_EINVAL, "KS adjoint plan must not be NULL");
+  if (!u0 || !uT) return kfail(SWEPT_EINVAL, "u0 and uT must not be NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t total = (int64_t)a->batch * a->n;
+  const size_t state = (size_t)total * sizeof(double);
+  // leading classic steps: u_0 .. u_r kept for the reverse sweep
+  hipError_t e = hipMemcpyAsync(a->rem, u0, state, hipMemcpyDeviceToDevice, st);
+  for (int m = 0; m < a->r && e == hipSuccess; ++m) {
+    const double* um = a->rem + (size_t)m * total;
+    hipLaunchKernelGGL(swept::ksadj::rem_pred_kernel, grid_for(total), dim3(kThreads), 0, st, um, a->tmp, a->k,
+                       a->n, total);
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    hipLaunchKernelGGL(swept::ksadj::rem_final_kernel, grid_for(total), dim3(kThreads), 0, st, um, a->tmp,
+                       a->rem + (size_t)(m + 1) * total, a->k, a->n, total);
+    e = hipGetLastError();
+  }
+  const double* ur = a->rem + (size_t)a->r * total;
+  const size_t pslots = (size_t)a->batch * 2 * (size_t)a->nt * kSL;
+  if (a->K == 0) {
+    if (e == hipSuccess) e = hipMemcpyAsync(uT, ur, state, hipMemcpyDeviceToDevice, st);
+  } else {
+    for (int p = 0; p <= a->K && e == hipSuccess; ++p) {
+      const double* ck_in = p > 0 ? a->ckpt + (size_t)(p - 1) * pslots : nullptr;
+      double* ck_out = p < a->K ? a->ckpt + (size_t)p * pslots : nullptr;
+      auto kern = p == 0 ? swept::ksadj::region_kernel<0, false, true>
+                         : (p == a->K ? swept::ksadj::region_kernel<0, true, false>
+                                      : swept::ksadj::region_kernel<0, true, true>);
+      hipLaunchKernelGGL(kern, dim3((unsigned)(a->batch * a->nt)), dim3(kW), 0, st, ur, static_cast<double*>(uT),
+                         ck_in, ck_out, nullptr, nullptr, nullptr, a->k, a->c, a->n, a->nt, p);
+      e = hipGetLastError();
+    }
+  }
+  if (e != hipSuccess) return khip(e, "swept_ks_forward_ckpt");
+  a->have_forward = true;
+  return SWEPT_OK;
+}
+
+int swept_ks_adjoint_run(swept_ks_adjoint a, const void* g_uT, void* g_u0, void* stream) {
+  if (!a) return kfail(SWEPT_EINVAL, "KS adjoint plan must not be NULL");
+  if (!g_uT || !g_u0) return kfail(SWEPT_EINVAL, "g_uT and g_u0 must not be NULL");
+  if (!a->have_forward) return kfail(SWEPT_EINVAL, "swept_ks_forward_ckpt must run first");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t total = (int64_t)a->batch * a->n;
+  const size_t state = (size_t)total * sizeof(double);
+  const size_t pslots = (size_t)a->batch * 2 * (size_t)a->nt * kSL;
+  hipError_t e = hipSuccess;
+  // adjoint at step r: from the swept sweep (or g_uT itself when T < 8)
+  double* lam_r = a->r > 0 ? a->lam_a : static_cast<double*>(g_u0);
+  if (a->K == 0) {
+    e = hipMemcpyAsync(lam_r, g_uT, state, hipMemcpyDeviceToDevice, st);
+  } else {
+    const double* ur = a->rem + (size_t)a->r * total;
+    for (int p = a->K; p >= 0 && e == hipSuccess; --p) {
+      const double* ck_in = p > 0 ? a->ckpt + (size_t)(p - 1) * pslots : nullptr;
+      auto kern = p == 0 ? swept::ksadj::region_kernel<1, false, true>
+                         : (p == a->K ? swept::ksadj::region_kernel<1, true, false>
+                                      : swept::ksadj::region_kernel<1, true, true>);
+      hipLaunchKernelGGL(kern, dim3((unsigned)(a->batch * a->nt)), dim3(kW), 0, st, ur, nullptr, ck_in, nullptr,
+                         static_cast<const double*>(g_uT), a->lam_slots, lam_r, a->k, a->c, a->n, a->nt, p);
+      e = hipGetLastError();
+    }
+  }
+  // leading classic steps backwards, m = r-1 .. 0
+  double* lin = lam_r;
+  for (int m = a->r - 1; m >= 0 && e == hipSuccess; --m) {
+    const double* um = a->rem + (size_t)m * total;
+    double* lout = m == 0 ? static_cast<double*>(g_u0) : (lin == a->lam_a ? a->lam_b : a->lam_a);
+    hipLaunchKernelGGL(swept::ksadj::rem_mu_kernel, grid_for(total), dim3(kThreads), 0, st, um, lin, a->tmp, a->k,
+                       a->c, a->n, total);
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    hipLaunchKernelGGL(swept::ksadj::rem_lam_kernel, grid_for(total), dim3(kThreads), 0, st, um, lin, a->tmp,
+                       lout, a->k, a->c, a->n, total);
+    e = hipGetLastError();
+    lin = lout;
+  }
+  if (e != hipSuccess) return khip(e, "swept_ks_adjoint_run");
+  return SWEPT_OK;
+}
+
+int swept_ks_adjoint_info(swept_ks_adjoint a, size_t* checkpoint_bytes, int* tile_width, int* steps_per_cycle,
+                          int64_t* leading_classic_steps) {
+  if (!a) return kfail(SWEPT_EINVAL, "KS adjoint plan must not be NULL");
+  if (checkpoint_bytes) *checkpoint_bytes = a->ckpt_bytes;
+  if (tile_width) *tile_width = kW;
+  if (steps_per_cycle) *steps_per_cycle = swept::ksadj::kH / 2;
+  if (leading_classic_steps) *leading_classic_steps = a->r;
+  return SWEPT_OK;
+}
+
+void swept_ks_adjoint_destroy(swept_ks_adjoint a) {
+  if (!a) return;
+  ks_free(a);
+}
+
+}  // extern "C"

@@ -173,6 +173,21 @@ def heat_adjoint(batch: int = 64, n: int = 2 ** 18, seed: int = 4, target_seed: 
     return u0, alpha, u0t, alpha_t, dt, dx, steps
 
 
+def ks_adjoint(batch: int = 1, n: int = 2 ** 20, seed: int = 6, target_seed: int = 7, steps: int = 20000):
+    """Returns (u0[batch,n], u0_target_source[batch,n], dt, dx, steps) for the KS
+    gradient workload: the KS initial state of the forward workload (dx = 0.5,
+    dt = 0.005) with seeded noise per grid; the target y is produced by running
+    the forward scheme from the second set of states."""
+    dx = 0.5
+    dt = 0.005
+    x = np.arange(n, dtype=np.float64) * dx
+    base = np.cos(x / 16.0) * (1.0 + np.sin(x / 16.0))
+    rng = _rng(seed)
+    u0 = np.stack([base + 1e-3 * rng.standard_normal(n) for _ in range(batch)])
+    rt = _rng(target_seed)
+    u0t = np.stack([base + 1e-3 * rt.standard_normal(n) for _ in range(batch)])
+    return u0, u0t, dt, dx, steps
+
 def dyadic_grid(n: int, seed: int, lo: int = -64, hi: int = 64) -> np.ndarray:
     """Small integer-valued grid: every FTCS step at Fo = 1/4 is then exact in FP64."""
     return _rng(seed).integers(lo, hi + 1, size=n).astype(np.float64)

@@ -323,6 +323,114 @@ def swept_heat(u0, alpha, steps: int, dt: float, dx: float):
     return _SWEPT_HEAT_FN.apply(u0, alpha, int(steps), float(dt), float(dx))
 
 
+def swept_ks_adjoint_create(batch: int, n: int, dtype, dt: float, dx: float, steps: int) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    check(_lib.lib().swept_ks_adjoint_create(ctypes.byref(h), int(batch), int(n), _dtype_code(dtype), float(dt),
+                                             float(dx), int(steps)))
+    return h
+
+
+def swept_ks_forward_ckpt(adj, u0, uT, stream=None) -> None:
+    check(_lib.lib().swept_ks_forward_ckpt(adj, ctypes.c_void_p(u0.data_ptr()), ctypes.c_void_p(uT.data_ptr()),
+                                           _stream_ptr(u0, stream)))
+
+
+def swept_ks_adjoint_run(adj, g_uT, g_u0, stream=None) -> None:
+    check(_lib.lib().swept_ks_adjoint_run(adj, ctypes.c_void_p(g_uT.data_ptr()), ctypes.c_void_p(g_u0.data_ptr()),
+                                          _stream_ptr(g_uT, stream)))
+
+
+def swept_ks_adjoint_info(adj) -> dict:
+    cb, w, spc, r = ctypes.c_size_t(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+    check(_lib.lib().swept_ks_adjoint_info(adj, ctypes.byref(cb), ctypes.byref(w), ctypes.byref(spc),
+                                           ctypes.byref(r)))
+    return {"checkpoint_bytes": cb.value, "tile_width": w.value, "steps_per_cycle": spc.value,
+            "leading_classic_steps": r.value}
+
+
+def swept_ks_adjoint_destroy(adj) -> None:
+    if adj:
+        _lib.lib().swept_ks_adjoint_destroy(adj)
+
+
+class KsAdjointPlan:
+    """Checkpointed swept forward and reverse sweep for a batch of KS grids."""
+
+    def __init__(self, batch: int, n: int, dt: float, dx: float, steps: int):
+        self.batch, self.n, self.steps = int(batch), int(n), int(steps)
+        self._h = swept_ks_adjoint_create(batch, n, "f64", dt, dx, steps)
+        self.info = swept_ks_adjoint_info(self._h)
+
+    def _check(self, t, shape):
+        import torch
+        if not t.is_cuda or t.dtype != torch.float64 or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous float64 device tensor of shape {shape}")
+
+    def forward(self, u0, uT, stream=None):
+        self._check(u0, (self.batch, self.n))
+        self._check(uT, (self.batch, self.n))
+        if u0.data_ptr() == uT.data_ptr():
+            raise ValueError("u0 and uT may not alias")
+        swept_ks_forward_ckpt(self._h, u0, uT, stream)
+        return uT
+
+    def adjoint(self, g_uT, g_u0, stream=None):
+        self._check(g_uT, (self.batch, self.n))
+        self._check(g_u0, (self.batch, self.n))
+        if g_uT.data_ptr() == g_u0.data_ptr():
+            raise ValueError("g_uT and g_u0 may not alias")
+        swept_ks_adjoint_run(self._h, g_uT, g_u0, stream)
+        return g_u0
+
+    def close(self):
+        if self._h:
+            swept_ks_adjoint_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _swept_ks_fn():
+    import torch
+
+    class SweptKsFn(torch.autograd.Function):
+        """u_T of a batch of periodic KS grids (swept forward, checkpointed);
+        backward is the hand-written swept adjoint, returning dJ/du_0."""
+
+        @staticmethod
+        def forward(ctx, u0, steps, dt, dx):
+            u0 = u0.contiguous()
+            plan = KsAdjointPlan(u0.shape[0], u0.shape[1], dt, dx, steps)
+            uT = torch.empty_like(u0)
+            plan.forward(u0, uT)
+            ctx.plan = plan
+            return uT
+
+        @staticmethod
+        def backward(ctx, g_uT):
+            plan = ctx.plan
+            g_u0 = torch.empty((plan.batch, plan.n), dtype=torch.float64, device=g_uT.device)
+            plan.adjoint(g_uT.contiguous(), g_u0)
+            return g_u0, None, None, None
+
+    return SweptKsFn
+
+
+_SWEPT_KS_FN = None
+
+
+def swept_ks(u0, steps: int, dt: float, dx: float):
+    """Differentiable swept KS run: u0 [batch, n] float64."""
+    global _SWEPT_KS_FN
+    if _SWEPT_KS_FN is None:
+        _SWEPT_KS_FN = _swept_ks_fn()
+    return _SWEPT_KS_FN.apply(u0, int(steps), float(dt), float(dx))
+
+
 class Plan:
     """Owns a swept plan; validates tensors before handing them to the C ABI."""
 

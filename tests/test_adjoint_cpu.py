@@ -25,3 +25,26 @@ def test_adjoint_null_handles():
     assert lib.swept_adjoint_run(None, None, None, None, None) == _lib.SWEPT_EINVAL
     assert lib.swept_adjoint_info(None, None, None, None, None) == _lib.SWEPT_EINVAL
     lib.swept_adjoint_destroy(None)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 1024, 1, 0.005, 0.5, 100), _lib.SWEPT_EINVAL),        # batch
+    ((1, 1000, 1, 0.005, 0.5, 100), _lib.SWEPT_EUNSUPPORTED),  # n not a multiple of 64
+    ((1, 32, 1, 0.005, 0.5, 100), _lib.SWEPT_EUNSUPPORTED),    # n below one tile
+    ((1, 1024, 0, 0.005, 0.5, 100), _lib.SWEPT_EUNSUPPORTED),  # f32
+    ((1, 1024, 1, 0.005, 0.5, 0), _lib.SWEPT_EINVAL),          # steps
+    ((1, 1024, 1, 0.005, 0.0, 10), _lib.SWEPT_EINVAL),         # dx
+    ((1, 1024, 1, float("nan"), 0.5, 10), _lib.SWEPT_EINVAL),  # dt
+])
+def test_ks_adjoint_create_rejects(args, code):
+    h = ctypes.c_void_p()
+    assert _lib.lib().swept_ks_adjoint_create(ctypes.byref(h), *args) == code
+    assert not h.value
+
+
+def test_ks_adjoint_null_handles():
+    lib = _lib.lib()
+    assert lib.swept_ks_forward_ckpt(None, None, None, None) == _lib.SWEPT_EINVAL
+    assert lib.swept_ks_adjoint_run(None, None, None, None) == _lib.SWEPT_EINVAL
+    assert lib.swept_ks_adjoint_info(None, None, None, None, None) == _lib.SWEPT_EINVAL
+    lib.swept_ks_adjoint_destroy(None)

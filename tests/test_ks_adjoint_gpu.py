@@ -1,0 +1,166 @@
+"""Swept KS adjoint on the GPU (reverse sweep of the periodic KS RK2 scheme,
+arXiv 1612.02495 Sec. 4.1 and Appendix) against the FP64 CPU reverse sweep
+bit for bit, and, at the full gradient workload (N = 2^20, 2e4 steps),
+against central differences of the swept forward run."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_02495_amd import KsAdjointPlan, Plan, inputs, swept_ks
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DT, DX = 0.005, 0.5
+
+
+def _states(batch, n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.arange(n) * DX
+    base = np.cos(x / 16.0) * (1.0 + np.sin(x / 16.0))
+    u0 = base + 1e-3 * rng.standard_normal((batch, n))
+    y = base + 0.1 * rng.standard_normal((batch, n))
+    return u0, y
+
+
+def _grad(plan, u0, y):
+    du0 = torch.tensor(u0, device="cuda")
+    uT = torch.empty_like(du0)
+    plan.forward(du0, uT)
+    g_uT = (uT - torch.tensor(y, device="cuda")).contiguous()
+    g_u0 = torch.empty_like(du0)
+    plan.adjoint(g_uT, g_u0)
+    torch.cuda.synchronize()
+    return uT.cpu().numpy(), g_u0.cpu().numpy()
+
+
+# (n, steps, batch): fewer steps than one phase (classic only), whole phases
+# only, phases plus leading classic steps, one tile (the ring closes on
+# itself), several tiles, several grids
+CASES = [(64, 3, 1), (64, 8, 1), (64, 30, 2), (128, 17, 1), (192, 61, 3), (256, 100, 2), (1024, 250, 2),
+         (4096, 411, 1)]
+
+
+@pytest.mark.parametrize("n,steps,batch", CASES)
+def test_ks_adjoint_equals_cpu_reverse_sweep(n, steps, batch):
+    print(f"ks adjoint n={n} steps={steps} batch={batch}", flush=True)
+    u0, y = _states(batch, n, n * 7 + steps)
+    plan = KsAdjointPlan(batch, n, DT, DX, steps)
+    assert plan.info["steps_per_cycle"] == 8 and plan.info["leading_classic_steps"] == steps % 8
+    uT, g = _grad(plan, u0, y)
+    for b in range(batch):
+        assert np.array_equal(uT[b], oracle.ks(u0[b], DT, DX, steps)), f"grid {b}: u_T differs"
+        J, go = oracle.ks_adjoint(u0[b], y[b], DT, DX, steps)
+        assert np.array_equal(g[b], go), f"grid {b}: max |dJ/du0 diff| {np.max(np.abs(g[b] - go))}"
+    plan.close()
+
+
+def test_ks_adjoint_rerun_and_plan_reuse():
+    # a second forward/adjoint pair on the same plan (slots and checkpoints rewritten) gives the same bits
+    n, steps = 256, 45
+    u0, y = _states(2, n, 11)
+    plan = KsAdjointPlan(2, n, DT, DX, steps)
+    uT1, g1 = _grad(plan, u0, y)
+    u0b, yb = _states(2, n, 12)
+    _grad(plan, u0b, yb)
+    uT2, g2 = _grad(plan, u0, y)
+    assert np.array_equal(uT1, uT2) and np.array_equal(g1, g2)
+
+
+def test_ks_adjoint_full_width_vs_oracle():
+    # all 16384 tiles of the gradient workload's grid, over 203 steps (25 phases + 3 classic)
+    u0, u0t, dt, dx, _ = inputs.ks_adjoint(batch=1, n=2 ** 20)
+    steps = 203
+    print("ks adjoint n=2^20 steps=203", flush=True)
+    plan = KsAdjointPlan(1, 2 ** 20, dt, dx, steps)
+    uT, g = _grad(plan, u0, u0t)
+    assert np.array_equal(uT[0], oracle.ks(u0[0], dt, dx, steps))
+    _, go = oracle.ks_adjoint(u0[0], u0t[0], dt, dx, steps)
+    assert np.array_equal(g[0], go), f"max |dJ/du0 diff| {np.max(np.abs(g[0] - go))}"
+
+
+def test_ks_adjoint_full_workload_central_differences():
+    # The gradient workload (N = 2^20, 2e4 steps, t = 100) and a tenth of its
+    # horizon (t = 10): dJ/du0 . d against difference quotients of J computed
+    # with the swept forward run of the main engine.
+    #  * t = 10: the second-order central quotient agrees to about 1e-9 over
+    #    h = 1e-4 .. 1e-5 (CPU oracle at N = 4096); bar 1e-6.
+    #  * t = 100: the flow is chaotic and tangent perturbations grow by about
+    #    1e7.  Rounding differences of the two forward runs grow alike and put
+    #    a noise floor of about 1e-13 / h on the relative error at this size
+    #    (measured: 1.5e-4, 1.7e-5, 3.3e-4 at h = 1e-7, 1e-8, 1e-9 with the
+    #    central quotient), so the fourth-order quotient
+    #    (8 (J(h) - J(-h)) - (J(2h) - J(-2h))) / (12 h) at h = 1e-7 .. 2e-7
+    #    is used, whose truncation (h A)^4 with h A ~ 1e-2 stays near 1e-7;
+    #    bar 1e-5.
+    u0, u0t, dt, dx, steps = inputs.ks_adjoint(batch=1, n=2 ** 20)
+    n = u0.shape[1]
+    p = Plan(n, "ks", torch.float64, dt, dx, tile_width=1024)
+    rng = np.random.default_rng(21)
+    for T, hs, order, bar in ((steps // 10, (1e-4, 1e-5), 2, 1e-6), (steps, (2e-7, 1e-7), 4, 1e-5)):
+        print(f"ks adjoint n=2^20 steps={T}", flush=True)
+
+        def fwd(u):
+            v = torch.tensor(u, device="cuda")
+            p.run(v, T)
+            torch.cuda.synchronize()
+            return v.cpu().numpy()
+
+        y = fwd(u0t[0])
+        plan = KsAdjointPlan(1, n, dt, dx, T)
+        uT, g = _grad(plan, u0, y[None, :])
+        assert np.array_equal(uT[0], fwd(u0[0]))  # checkpointed forward = main swept engine, bit for bit
+        # the reverse sweep is linear in g_uT and scaling by 2 is exact: 2 g_uT gives 2 dJ/du0 bit for bit
+        g2 = torch.empty((1, n), dtype=torch.float64, device="cuda")
+        plan.adjoint(torch.tensor(2.0 * (uT - y[None, :]), device="cuda"), g2)
+        torch.cuda.synchronize()
+        assert np.array_equal(g2.cpu().numpy(), 2.0 * g)
+        plan.close()
+
+        def J(u):
+            return 0.5 * math.fsum(((fwd(u) - y) ** 2).tolist())
+
+        d = rng.standard_normal(n)
+        d /= np.linalg.norm(d)
+        gd = float(np.dot(g[0], d))
+        errs = []
+        for h in hs:
+            d1 = J(u0[0] + h * d) - J(u0[0] - h * d)
+            if order == 2:
+                fd = d1 / (2 * h)
+            else:
+                d2 = J(u0[0] + 2 * h * d) - J(u0[0] - 2 * h * d)
+                fd = (8 * d1 - d2) / (12 * h)
+            errs.append(abs(fd - gd) / abs(gd))
+            print(f"steps {T} h={h:g} order {order}: dJ/du0 . d swept {gd:.12e} FD {fd:.12e} rel {errs[-1]:.2e}",
+                  flush=True)
+        assert min(errs) <= bar, errs
+
+
+def test_swept_ks_autograd_and_gradcheck():
+    n, steps, batch = 64, 19, 2
+    u0, y = _states(batch, n, 3)
+    x = torch.tensor(u0, device="cuda", requires_grad=True)
+    yt = torch.tensor(y, device="cuda")
+    uT = swept_ks(x, steps, DT, DX)
+    J = 0.5 * ((uT - yt) ** 2).sum()
+    J.backward()
+    for b in range(batch):
+        _, go = oracle.ks_adjoint(u0[b], y[b], DT, DX, steps)
+        assert np.array_equal(x.grad[b].cpu().numpy(), go)
+    f = lambda a: swept_ks(a, steps, DT, DX)
+    assert torch.autograd.gradcheck(f, (torch.tensor(u0, device="cuda", requires_grad=True),),
+                                    eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+def test_ks_adjoint_errors():
+    plan = KsAdjointPlan(1, 128, DT, DX, 20)
+    g = torch.zeros((1, 128), dtype=torch.float64, device="cuda")
+    with pytest.raises(Exception):   # no forward pass yet
+        plan.adjoint(g, torch.empty_like(g))
+    with pytest.raises(ValueError):  # aliasing
+        plan.forward(g, g)
+    with pytest.raises(ValueError):  # shape
+        plan.forward(torch.zeros((1, 64), dtype=torch.float64, device="cuda"), g)
