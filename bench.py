@@ -130,7 +130,7 @@ def run_adjoint(args, wl):
     if not args.no_cpu_baseline:
         import time as _time
         import oracle
-        cs = args.cpu_steps or 100
+        cs = args.cpu_steps or 4000
         t0 = _time.perf_counter()
         oracle.heat_adjoint(u0[0], u0t[0], alpha[0], dt, dx, cs)
         el = _time.perf_counter() - t0
@@ -213,7 +213,7 @@ def run_ks_adjoint(args, wl):
     if not args.no_cpu_baseline:
         import time as _time
         import oracle
-        cs = args.cpu_steps or 120
+        cs = args.cpu_steps or 400
         t0 = _time.perf_counter()
         oracle.ks_adjoint(u0[0], u0t[0], dt, dx, cs)
         el = _time.perf_counter() - t0

@@ -286,6 +286,7 @@ typedef struct swept_adjoint_s* swept_adjoint;
  * swept_adjoint_create -- plan the gradient of a functional of u_T for a
  * batch of `batch` periodic heat FTCS grids of n points each (Eq. HeatDisc),
  * all with the same dt, dx and number of steps, each with its own alpha.
+ *   batch  1 .. 65535
  *   dtype  SWEPT_F64 (other types fail with EUNSUPPORTED)
  *   n      a positive multiple of 64
  *   steps  >= 1
@@ -343,6 +344,7 @@ typedef struct swept_ks_adjoint_s* swept_ks_adjoint;
  * q = u + (dt/2) f(u), u' = u + dt f(q), f the 5-point right-hand side, with
  * the constants of swept_plan_create for SWEPT_KS_RK2.  All grids share dt,
  * dx and the number of steps.
+ *   batch  1 .. 65535
  *   dtype  SWEPT_F64 (other types fail with EUNSUPPORTED)
  *   n      a positive multiple of 64
  *   steps  >= 1

@@ -15,7 +15,8 @@
 // slots out of place, into checkpoint p.  Reverse, for p = K .. 0, one fused
 // launch per phase: every tile
 //   1. recomputes its forward region (V then Lambda) from checkpoint p-1,
-//      keeping every tier of its own point in the lane's registers;
+//      keeping, for every tier, the Laplacian of the previous tier at its
+//      own point in the lane's registers;
 //   2. walks lambda down through the same region: its Lambda part first,
 //      taking the lambda values of later regions just outside each tier from
 //      lambda slots, then its V part, handing the two outermost values of each
@@ -55,16 +56,16 @@ __global__ void consts_kernel(const double* __restrict__ alpha, int batch, doubl
   k[b] = c;
 }
 
-// Whether tile point x is computed at diamond tier d (V part d <= h, Lambda
-// d > h).
-__device__ __forceinline__ bool in_row(int x, int d) {
-  if (d < kH) return x >= kA - d && x < kA + d;
-  if (d == kH) return true;
-  return x >= d - kH && x < kW - d + kH;
+// Lanes computed at diamond tier d: the gap [a-d, a+d) in the V part
+// (d <= h), [d-h, w-d+h) in the Lambda part.
+__host__ __device__ constexpr uint64_t row_bits(int d) {
+  return d <= kH ? wave::range_bits(kA - d, kA + d) : wave::range_bits(d - kH, kW - d + kH);
 }
 
+// Lanes [lo, lo + 2): the two points of an edge band.
+__host__ __device__ constexpr uint64_t pair_bits(int lo) { return wave::range_bits(lo, lo + 2); }
+
 // Lane x inside [lo, lo + 2): the two points of an edge band.
-__device__ __forceinline__ bool in_pair(int x, int lo) { return (unsigned)(x - lo) < 2u; }
 
 // One swept region of one tile, held in one wave64: lane x owns tile point x
 // and keeps the region's states u(x, d) in registers, tier by tier; the
@@ -85,27 +86,37 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
   using wave::dpp_move0;
   using wave::kDppWaveShl1;
   using wave::kDppWaveShr1;
+  using wave::lanes;
   using wave::pick;
-  constexpr int kDppWaveRor1 = 0x13C;  // lane i <- lane i-1, lane 0 <- lane 63
-  constexpr int kDppWaveRol1 = 0x134;  // lane i <- lane i+1, lane 63 <- lane 0
   const int x = threadIdx.x;
-  const int64_t b = blockIdx.x / nt;
-  const int64_t j = blockIdx.x % nt;
+  const int64_t j = blockIdx.x;  // tile
+  const int64_t b = blockIdx.y;  // grid of the batch
   const Consts<double> k = kb[b];
   const int par = p & 1;
   const int64_t origin = j * kW + (par ? kA : 0);
   const int64_t base = b * 2 * nt * kSL;
   const int64_t sL = base + (par ? (nt + j) * kSL : j * kSL);
-  const int64_t sR = base + (par ? ((j + 1) % nt) * kSL : (nt + j) * kSL);
+  const int64_t sR = base + (par ? (j + 1 == nt ? 0 : j + 1) * kSL : (nt + j) * kSL);
   int64_t gx = origin + x;
   if (gx >= n) gx -= n;
   const int64_t gidx = b * n + gx;
+  // this lane's outgoing slot entries (checkpoint bands in MODE 0, lambda
+  // bands in MODE 1): left side p = x, right side p = x - a + 1, one value
+  // per tier parity; a lane only stores where it owns a band point
+  double* const out = MODE == 0 ? ck_out : lam_slots;
+  double* const outL = out + sL + 2 * x;
+  double* const outR = out + sR + 2 * (x - kA + 1);
 
   // ------------------------------------------------ forward recompute --
-  double hist[2 * kH];  // u(x, d), d = 0 .. 2h-1 (MODE 0 keeps only the live row)
+  // MODE 1 keeps, for every tier d of the region, the Laplacian term of the
+  // dJ/dalpha sum at this lane's point, lap[d] = (u(x-1,d-1) + u(x+1,d-1)) -
+  // 2 u(x,d-1), formed from the same neighbour sum the update uses (IEEE
+  // addition commutes, so the bits equal those of the separate formula).
+  double lap[2 * kH];
+  double top = 0.0;  // the region's row at tier h
   double tipL = 0.0, tipR = 0.0;  // points -1 and w at tier h-1
   if constexpr (!HV) {
-    hist[kH] = ustart[gidx];
+    top = ustart[gidx];
   } else {
     // this lane's incoming band values, one per tier parity
     const int64_t src = x < kA ? sL + 2 * (x + 1) : sR + 2 * (x - kA);
@@ -116,50 +127,54 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
 #pragma unroll
     for (int t = 0; t < kH; ++t) {
       // band of tier t: [a-t-2, a-t) and [a+t, a+t+2)
-      row = pick(in_pair(x, kA - t - 2) || in_pair(x, kA + t), (t & 1) ? bv1 : bv0, row);
-      hist[t] = row;
+      row = pick(lanes(pair_bits(kA - t - 2) | pair_bits(kA + t)), (t & 1) ? bv1 : bv0, row);
       double lo = dpp_move0<kDppWaveShr1>(row), hi = dpp_move0<kDppWaveShl1>(row);
       if (t == kH - 1) {
-        lo = pick(x == 0, tipL, lo);
-        hi = pick(x == kW - 1, tipR, hi);
+        lo = pick(lanes(1ull), tipL, lo);
+        hi = pick(lanes(1ull << (kW - 1)), tipR, hi);
       }
-      row = heat_update(lo, row, hi, k);
+      const double sum = hi + lo;
+      if constexpr (MODE == 1) lap[t + 1] = sum - 2.0 * row;
+      row = k.fo * sum + k.c * row;  // heat_update(lo, row, hi)
     }
-    hist[kH] = row;
+    top = row;
   }
   if constexpr (HL) {
-    double row = hist[kH];
-    double o0 = 0.0, o1 = 0.0;  // MODE 0: this lane's outgoing band values
+    double row = top;
+    double c0 = 0.0, c1 = 0.0;  // MODE 0: this lane's outgoing band values, by tier parity
 #pragma unroll
     for (int m = 0; m < kH; ++m) {
       if (m > 0) {
         const double lo = dpp_move0<kDppWaveShr1>(row), hi = dpp_move0<kDppWaveShl1>(row);
-        row = heat_update(lo, row, hi, k);
-        hist[kH + m] = row;
+        const double sum = hi + lo;
+        if constexpr (MODE == 1) lap[kH + m] = sum - 2.0 * row;
+        row = k.fo * sum + k.c * row;  // heat_update(lo, row, hi)
       }
       if constexpr (MODE == 0) {
-        // band of Lambda tier m: [m, m+2) and [w-m-2, w-m)
-        const bool band = in_pair(x, m) || in_pair(x, kW - m - 2);
+        // bands of Lambda tier m: [m, m+2) and [w-m-2, w-m).  Collected in
+        // registers and stored once: storing each tier's two-lane pieces as
+        // they form costs more in small writes than the selects.
+        const bool band = lanes(pair_bits(m) | pair_bits(kW - m - 2));
         if (m & 1)
-          o1 = pick(band, row, o1);
+          c1 = pick(band, row, c1);
         else
-          o0 = pick(band, row, o0);
+          c0 = pick(band, row, c0);
       }
     }
     if constexpr (MODE == 0) {
       // left side p = x at tiers m = x-1, x; right side p = x-a+1 at m = w-x-2, w-x-1
       if (x <= kA) {
-        if (x <= kH - 1) ck_out[sL + 2 * x + (x & 1)] = (x & 1) ? o1 : o0;
-        if (x >= 1) ck_out[sL + 2 * x + ((x - 1) & 1)] = ((x - 1) & 1) ? o1 : o0;
+        if (x <= kH - 1) outL[x & 1] = (x & 1) ? c1 : c0;
+        if (x >= 1) outL[(x - 1) & 1] = ((x - 1) & 1) ? c1 : c0;
       }
       if (x >= kA - 1) {
         const int m0 = kW - x - 2, m1 = kW - x - 1;
-        if (m0 >= 0) ck_out[sR + 2 * (x - kA + 1) + (m0 & 1)] = (m0 & 1) ? o1 : o0;
-        if (m1 <= kH - 1) ck_out[sR + 2 * (x - kA + 1) + (m1 & 1)] = (m1 & 1) ? o1 : o0;
+        if (m0 >= 0) outR[m0 & 1] = (m0 & 1) ? c1 : c0;
+        if (m1 <= kH - 1) outR[m1 & 1] = (m1 & 1) ? c1 : c0;
       }
     }
   } else if constexpr (MODE == 0) {
-    uT[gidx] = hist[kH];
+    uT[gidx] = top;
   }
   if constexpr (MODE == 1) {
     // --------------------------------------------------- adjoint sweep --
@@ -176,9 +191,9 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
       ltipR = lam_slots[sR + 2 * kH + 1];
     }
     double lam = 0.0, acc = 0.0;
-    double oL0 = 0.0, oL1 = 0.0, oR0 = 0.0, oR1 = 0.0;
+    double o0 = 0.0, o1 = 0.0;  // this lane's outgoing lambda, by tier parity
     if constexpr (HL)
-      lam = pick(in_pair(x, kH - 2) || in_pair(x, kW - kH), (kH & 1) ? in1 : in0, lam);
+      lam = pick(lanes(pair_bits(kH - 2) | pair_bits(kW - kH)), (kH & 1) ? in1 : in0, lam);
     else
       lam = gT[gidx];  // lambda at the region's top tier h
 #pragma unroll
@@ -186,56 +201,48 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
       if (HL || d < kH) {  // lambda at tier d from tier d+1
         double lo = dpp_move0<kDppWaveShr1>(lam), hi = dpp_move0<kDppWaveShl1>(lam);
         if (HL && d == kH) {
-          lo = pick(x == 0, ltipL, lo);
-          hi = pick(x == kW - 1, ltipR, hi);
+          lo = pick(lanes(1ull), ltipL, lo);
+          hi = pick(lanes(1ull << (kW - 1)), ltipR, hi);
         }
         lam = heat_update(lo, lam, hi, k);
       }
       if (HV || d != kH) {  // dJ/dalpha term lambda(x,d) (L u)(x, d-1)
-        // Rotations rather than the shifts of the recompute: the shifted rows
-        // of the recompute are then not kept alive for this reuse, which
-        // would triple the registers the history needs.  The wrapped lanes
-        // (0 and w-1) are outside every row that reaches them, except at
-        // d = h where the triangle tips replace them.
-        const double um = hist[d - 1];
-        double ul = dpp_move0<kDppWaveRor1>(um), ur = dpp_move0<kDppWaveRol1>(um);
-        if (d == kH) {
-          ul = pick(x == 0, tipL, ul);
-          ur = pick(x == kW - 1, tipR, ur);
-        }
-        const double lap = (ul + ur) - 2.0 * um;
-        acc = pick(in_row(x, d), acc + lam * lap, acc);
+        acc = pick(lanes(row_bits(d)), acc + lam * lap[d], acc);
         // settle this tier's sum here so that no term waits in a register
         asm volatile("" : "+v"(acc));
       }
       if (HV && d <= kH) {
-        // the two outermost values on each side of gap(d) go to the previous phase
-        const bool ol = in_pair(x, kA - d), orr = in_pair(x, kA + d - 2);
-        if (d & 1) {
-          oL1 = pick(ol, lam, oL1);
-          oR1 = pick(orr, lam, oR1);
-        } else {
-          oL0 = pick(ol, lam, oL0);
-          oR0 = pick(orr, lam, oR0);
-        }
+        // the two outermost values on each side of gap(d) go to the previous
+        // phase.  A lane hands on at most two tiers over both sides, of
+        // different parity (and the same lambda where both sides take one
+        // tier), so one register per parity collects them.
+        const bool hand = lanes(pair_bits(kA - d) | pair_bits(kA + d - 2));
+        if (d & 1)
+          o1 = pick(hand, lam, o1);
+        else
+          o0 = pick(hand, lam, o0);
+        // select here, not at the stores: deferred selects keep every tier's
+        // lambda and mask live
+        asm volatile("" : "+v"(o0), "+v"(o1));
       }
       if (!HV && d == kH) g_ur[gidx] = lam;
       if (HL && d > kH) {
         const int m = d - kH;
-        lam = pick(in_pair(x, m - 2) || in_pair(x, kW - m), (m & 1) ? in1 : in0, lam);
+        lam = pick(lanes(pair_bits(m - 2) | pair_bits(kW - m)), (m & 1) ? in1 : in0, lam);
       }
     }
     if constexpr (HV) {
-      // left: lanes x <= a at d = a-x, a-x+1; right: lanes x >= a-1 at d = x-a+1, x-a+2 (d in [1, h])
+      // left side p = x: lanes x <= a at d = a-x, a-x+1; right side
+      // p = x-a+1: lanes x >= a-1 at d = x-a+1, x-a+2 (d in [1, h])
       if (x <= kA) {
         const int d0 = kA - x, d1 = kA - x + 1;
-        if (d0 >= 1) lam_slots[sL + 2 * x + (d0 & 1)] = (d0 & 1) ? oL1 : oL0;
-        if (d1 <= kH) lam_slots[sL + 2 * x + (d1 & 1)] = (d1 & 1) ? oL1 : oL0;
+        if (d0 >= 1) outL[d0 & 1] = (d0 & 1) ? o1 : o0;
+        if (d1 <= kH) outL[d1 & 1] = (d1 & 1) ? o1 : o0;
       }
       if (x >= kA - 1) {
         const int d0 = x - kA + 1, d1 = x - kA + 2;
-        if (d0 >= 1) lam_slots[sR + 2 * (x - kA + 1) + (d0 & 1)] = (d0 & 1) ? oR1 : oR0;
-        if (d1 <= kH) lam_slots[sR + 2 * (x - kA + 1) + (d1 & 1)] = (d1 & 1) ? oR1 : oR0;
+        if (d0 >= 1) outR[d0 & 1] = (d0 & 1) ? o1 : o0;
+        if (d1 <= kH) outR[d1 & 1] = (d1 & 1) ? o1 : o0;
       }
     }
     // per-tile sum in a fixed order (x += x + s, s = 32 .. 1), added to this
@@ -357,7 +364,7 @@ int swept_adjoint_create(swept_adjoint* out, int32_t batch, int64_t n, int dtype
                          int64_t steps) {
   if (!out) return afail(SWEPT_EINVAL, "out must not be NULL");
   *out = nullptr;
-  if (batch < 1) return afail(SWEPT_EINVAL, "batch must be >= 1");
+  if (batch < 1 || batch > 65535) return afail(SWEPT_EINVAL, "batch must be in [1, 65535]");
   if (dtype != SWEPT_F64) return afail(SWEPT_EUNSUPPORTED, "the adjoint is built for SWEPT_F64");
   if (n < kW || n % kW != 0) return afail(SWEPT_EUNSUPPORTED, "n must be a positive multiple of 64");
   if (steps < 1) return afail(SWEPT_EINVAL, "steps must be >= 1");
@@ -432,7 +439,7 @@ int swept_forward_ckpt(swept_adjoint a, const void* u0, const double* alpha, voi
       double* ck_out = p < a->K ? a->ckpt + (size_t)p * pslots : nullptr;
       auto kern = p == 0 ? swept::adj::region_kernel<0, false, true>
                   : (p == a->K ? swept::adj::region_kernel<0, true, false> : swept::adj::region_kernel<0, true, true>);
-      hipLaunchKernelGGL(kern, dim3((unsigned)(a->batch * a->nt)), dim3(kW), 0, st, ur, static_cast<double*>(uT), ck_in,
+      hipLaunchKernelGGL(kern, dim3((unsigned)a->nt, (unsigned)a->batch), dim3(kW), 0, st, ur, static_cast<double*>(uT), ck_in,
                          ck_out, nullptr, nullptr, nullptr, nullptr, k, a->n, a->nt, p);
       e = hipGetLastError();
     }
@@ -463,7 +470,7 @@ int swept_adjoint_run(swept_adjoint a, const void* g_uT, void* g_u0, double* g_a
       const double* ck_in = p > 0 ? a->ckpt + (size_t)(p - 1) * pslots : nullptr;
       auto kern = p == 0 ? swept::adj::region_kernel<1, false, true>
                   : (p == a->K ? swept::adj::region_kernel<1, true, false> : swept::adj::region_kernel<1, true, true>);
-      hipLaunchKernelGGL(kern, dim3((unsigned)(a->batch * a->nt)), dim3(kW), 0, st, ur, nullptr, ck_in, nullptr,
+      hipLaunchKernelGGL(kern, dim3((unsigned)a->nt, (unsigned)a->batch), dim3(kW), 0, st, ur, nullptr, ck_in, nullptr,
                          static_cast<const double*>(g_uT), a->lam_slots, lam_r, a->tiles, k, a->n, a->nt, p);
       e = hipGetLastError();
     }

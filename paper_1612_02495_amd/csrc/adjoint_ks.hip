@@ -69,7 +69,8 @@ __device__ __forceinline__ double jt(double v, double wl2, double wl1, double w,
   return (((dm * wl1 + dp * wr1) + c.c0 * w) + c.c2 * wl2) + c.c2 * wr2;
 }
 
-__device__ __forceinline__ bool in_range(int x, int lo, int hi) { return x >= lo && x < hi; }
+using wave::lanes;
+using wave::range_bits;
 
 // The values two and one lanes to the left and right (zero past the wave).
 struct Nb {
@@ -87,18 +88,18 @@ __device__ __forceinline__ Nb nbrs(double v) {
 }
 
 // Points -2, -1 and w, w+1 of a row that reaches past the tile.
-__device__ __forceinline__ void fix_ends(Nb& b, int x, double tl0, double tl1, double tr0, double tr1) {
+__device__ __forceinline__ void fix_ends(Nb& b, double tl0, double tl1, double tr0, double tr1) {
   using wave::pick;
-  b.l1 = pick(x == 0, tl1, b.l1);
-  b.l2 = pick(x == 0, tl0, pick(x == 1, tl1, b.l2));
-  b.r1 = pick(x == kW - 1, tr0, b.r1);
-  b.r2 = pick(x == kW - 1, tr1, pick(x == kW - 2, tr0, b.r2));
+  b.l1 = pick(lanes(1ull), tl1, b.l1);
+  b.l2 = pick(lanes(1ull), tl0, pick(lanes(2ull), tl1, b.l2));
+  b.r1 = pick(lanes(1ull << (kW - 1)), tr0, b.r1);
+  b.r2 = pick(lanes(1ull << (kW - 1)), tr1, pick(lanes(1ull << (kW - 2)), tr0, b.r2));
 }
 
 // Positions just outside Lambda tier t of a tile whose adjoint belongs to
 // later regions: [2t - 4, 2t) and [w - 2t, w - 2t + 4).
-__device__ __forceinline__ bool outside(int x, int t) {
-  return in_range(x, kS * t - 2 * kS, kS * t) || in_range(x, kW - kS * t, kW - kS * t + 2 * kS);
+__host__ __device__ constexpr uint64_t outside_bits(int t) {
+  return range_bits(kS * t - 2 * kS, kS * t) | range_bits(kW - kS * t, kW - kS * t + 2 * kS);
 }
 
 // One swept region of one tile in one wave64 (lane x = tile point x).
@@ -113,18 +114,24 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
               double* __restrict__ g_ur, Consts<double> k, JtCoef c, int64_t n, int64_t nt, int p) {
   using wave::pick;
   const int x = threadIdx.x;
-  const int64_t b = blockIdx.x / nt;
-  const int64_t j = blockIdx.x % nt;
+  const int64_t j = blockIdx.x;  // tile
+  const int64_t b = blockIdx.y;  // grid of the batch
   const int par = p & 1;
   const int64_t origin = j * kW + (par ? kA : 0);
   const int64_t base = b * 2 * nt * kSL;
   const int64_t sL = base + (par ? (nt + j) * kSL : j * kSL);
-  const int64_t sR = base + (par ? ((j + 1) % nt) * kSL : (nt + j) * kSL);
+  const int64_t sR = base + (par ? (j + 1 == nt ? 0 : j + 1) * kSL : (nt + j) * kSL);
   int64_t gx = origin + x;
   if (gx >= n) gx -= n;
   const int64_t gidx = b * n + gx;
   // this lane's entry in the incoming slots (one value per tier parity)
   const int64_t src = x < kA ? sL + 2 * (x + kS) : sR + 2 * (x - kA);
+  // this lane's outgoing slot entries (checkpoint bands in MODE 0, adjoint
+  // bands in MODE 1): left side p = x, right side p = x - a + 2, one value
+  // per tier parity; a lane only stores where it owns a band point
+  double* const out = MODE == 0 ? ck_out : lam_slots;
+  double* const outL = out + sL + 2 * x;
+  double* const outR = out + sR + 2 * (x - kA + kS);
 
   // ------------------------------------------------ forward recompute --
   double hist[2 * kH];  // u or q at (x, d), d = 0 .. 2h-1 (MODE 0 keeps only live tiers)
@@ -140,11 +147,11 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
 #pragma unroll
     for (int t = 0; t < kH; ++t) {
       // bands of tier t: [a-4-2t, a-2t) and [a+2t, a+2t+4)
-      const bool band = in_range(x, kA - 2 * kS - kS * t, kA - kS * t) || in_range(x, kA + kS * t, kA + kS * t + 2 * kS);
-      row = pick(band, (t & 1) ? bv1 : bv0, row);
+      const uint64_t band = range_bits(kA - 2 * kS - kS * t, kA - kS * t) | range_bits(kA + kS * t, kA + kS * t + 2 * kS);
+      row = pick(lanes(band), (t & 1) ? bv1 : bv0, row);
       hist[t] = row;
       Nb nb = nbrs(row);
-      if (t == kH - 1) fix_ends(nb, x, tl0, tl1, tr0, tr1);
+      if (t == kH - 1) fix_ends(nb, tl0, tl1, tr0, tr1);
       if ((t + 1) & 1)
         row = ks_predictor(nb.l2, nb.l1, row, nb.r1, nb.r2, k);
       else
@@ -154,7 +161,6 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
   }
   if constexpr (HL) {
     double row = hist[kH];
-    double o0 = 0.0, o1 = 0.0;  // MODE 0: this lane's outgoing band values
 #pragma unroll
     for (int m = 0; m < kH; ++m) {
       if (m > 0) {
@@ -166,24 +172,11 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
         hist[kH + m] = row;
       }
       if constexpr (MODE == 0) {
-        // bands of Lambda tier m: [2m, 2m+4) and [w-2m-4, w-2m)
-        const bool band = in_range(x, kS * m, kS * m + 2 * kS) || in_range(x, kW - kS * m - 2 * kS, kW - kS * m);
-        if (m & 1)
-          o1 = pick(band, row, o1);
-        else
-          o0 = pick(band, row, o0);
-      }
-    }
-    if constexpr (MODE == 0) {
-      // left side p = x (x < a+2) at tiers m = x/2 - 1, x/2; right side
-      // p = x - a + 2 (x >= a-2) at tiers m = ceil((w-4-x)/2) + 0, 1
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int ml = x / kS - 1 + e;
-        if (x < kA + kS && ml >= 0 && ml <= kH - 1) ck_out[sL + 2 * x + (ml & 1)] = (ml & 1) ? o1 : o0;
-        const int mr = (kW - x + 1) / kS - 2 + e;
-        if (x >= kA - kS && mr >= 0 && mr <= kH - 1)
-          ck_out[sR + 2 * (x - kA + kS) + (mr & 1)] = (mr & 1) ? o1 : o0;
+        // bands of Lambda tier m, stored by their lanes as they are formed:
+        // [2m, 2m+4) to the left side (p = x), [w-2m-4, w-2m) to the right
+        // side (p = x - a + 2), one entry per tier parity
+        if (lanes(range_bits(kS * m, kS * m + 2 * kS))) outL[m & 1] = row;
+        if (lanes(range_bits(kW - kS * m - 2 * kS, kW - kS * m))) outR[m & 1] = row;
       }
     }
   } else if constexpr (MODE == 0) {
@@ -203,35 +196,39 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
     }
     double lam = 0.0, lam2 = 0.0;  // adjoint at tiers d+1 and d+2
     if constexpr (HL)
-      lam = pick(outside(x, kH), (kH & 1) ? in1 : in0, lam);
+      lam = pick(lanes(outside_bits(kH)), (kH & 1) ? in1 : in0, lam);
     else
       lam = gT[gidx];  // the region's top tier h is u_T
-    double oL0 = 0.0, oL1 = 0.0, oR0 = 0.0, oR1 = 0.0;
+    double o0 = 0.0, o1 = 0.0;  // this lane's outgoing adjoint, by tier parity
 #pragma unroll
     for (int d = HL ? 2 * kH - 1 : kH; d >= (HV ? 1 : kH); --d) {
       if (HL || d < kH) {
         Nb nb = nbrs(lam);
-        if (HL && d == kH) fix_ends(nb, x, ll0, ll1, lr0, lr1);
+        if (HL && d == kH) fix_ends(nb, ll0, ll1, lr0, lr1);
         const double g = jt(hist[d], nb.l2, nb.l1, lam, nb.r1, nb.r2, c);
         const double nw = (d & 1) ? k.dt * g : (lam2 + lam) + k.dth * g;
         lam2 = lam;
         lam = nw;
         if (HL && d > kH) {
           const int t = d - kH;
-          lam = pick(outside(x, t), (t & 1) ? in1 : in0, lam);
+          lam = pick(lanes(outside_bits(t)), (t & 1) ? in1 : in0, lam);
         }
       }
       if (HV && d <= kH) {
         // the 4 outermost values on each side of gap(d) go to the previous phase
-        const bool ol = in_range(x, kA - kS * d, kA - kS * d + 2 * kS);
-        const bool orr = in_range(x, kA + kS * d - 2 * kS, kA + kS * d);
-        if (d & 1) {
-          oL1 = pick(ol, lam, oL1);
-          oR1 = pick(orr, lam, oR1);
-        } else {
-          oL0 = pick(ol, lam, oL0);
-          oR0 = pick(orr, lam, oR0);
-        }
+        // (lanes [a-2d, a-2d+4) and [a+2d-4, a+2d)).  A lane hands on at
+        // most two tiers over both sides, of different parity (and the same
+        // value where both sides take one tier), so one register per parity
+        // collects them.
+        const bool hand = lanes(range_bits(kA - kS * d, kA - kS * d + 2 * kS) |
+                                range_bits(kA + kS * d - 2 * kS, kA + kS * d));
+        if (d & 1)
+          o1 = pick(hand, lam, o1);
+        else
+          o0 = pick(hand, lam, o0);
+        // select here, not at the stores: deferred selects keep every tier's
+        // adjoint and mask live
+        asm volatile("" : "+v"(o0), "+v"(o1));
       }
       if (!HV && d == kH) g_ur[gidx] = lam;
     }
@@ -241,10 +238,10 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int dl = (kA - x + 1) / 2 + e;
-        if (x < kA + kS && dl >= 1 && dl <= kH) lam_slots[sL + 2 * x + (dl & 1)] = (dl & 1) ? oL1 : oL0;
+        if (x < kA + kS && dl >= 1 && dl <= kH) outL[dl & 1] = (dl & 1) ? o1 : o0;
         const int dr = (x - kA + 2) / 2 + e;
         if (x >= kA - kS && dr >= 1 && dr <= kH)
-          lam_slots[sR + 2 * (x - kA + kS) + (dr & 1)] = (dr & 1) ? oR1 : oR0;
+          outR[dr & 1] = (dr & 1) ? o1 : o0;
       }
     }
   }
@@ -358,14 +355,14 @@ int swept_ks_adjoint_create(swept_ks_adjoint* out, int32_t batch, int64_t n, int
                             int64_t steps) {
   if (!out) return kfail(SWEPT_EINVAL, "out must not be NULL");
   *out = nullptr;
-  if (batch < 1) return kfail(SWEPT_EINVAL, "batch must be >= 1");
+  if (batch < 1 || batch > 65535) return kfail(SWEPT_EINVAL, "batch must be in [1, 65535]");
   if (dtype != SWEPT_F64) return kfail(SWEPT_EUNSUPPORTED, "the KS adjoint is built for SWEPT_F64");
   if (n < kW || n % kW != 0) return kfail(SWEPT_EUNSUPPORTED, "n must be a positive multiple of 64");
   if (steps < 1) return kfail(SWEPT_EINVAL, "steps must be >= 1");
   if (!std::isfinite(dt) || !std::isfinite(dx) || dx == 0.0)
     return kfail(SWEPT_EINVAL, "dt, dx must be finite, dx != 0");
   const int64_t total = (int64_t)batch * n;
-  if ((total + kThreads - 1) / kThreads > 0x7fffffff || (int64_t)batch * (n / kW) > 0x7fffffff)
+  if ((total + kThreads - 1) / kThreads > 0x7fffffff || n / kW > 0x7fffffff)
     return kfail(SWEPT_EINVAL, "batch x n too large for one launch");
   auto* a = new (std::nothrow) swept_ks_adjoint_s();
   if (!a) return kfail(SWEPT_ENOMEM, "host allocation failed");
@@ -440,7 +437,7 @@ int swept_ks_forward_ckpt(swept_ks_adjoint a, const void* u0, void* uT, void* st
       auto kern = p == 0 ? swept::ksadj::region_kernel<0, false, true>
                          : (p == a->K ? swept::ksadj::region_kernel<0, true, false>
                                       : swept::ksadj::region_kernel<0, true, true>);
-      hipLaunchKernelGGL(kern, dim3((unsigned)(a->batch * a->nt)), dim3(kW), 0, st, ur, static_cast<double*>(uT),
+      hipLaunchKernelGGL(kern, dim3((unsigned)a->nt, (unsigned)a->batch), dim3(kW), 0, st, ur, static_cast<double*>(uT),
                          ck_in, ck_out, nullptr, nullptr, nullptr, a->k, a->c, a->n, a->nt, p);
       e = hipGetLastError();
     }
@@ -470,7 +467,7 @@ int swept_ks_adjoint_run(swept_ks_adjoint a, const void* g_uT, void* g_u0, void*
       auto kern = p == 0 ? swept::ksadj::region_kernel<1, false, true>
                          : (p == a->K ? swept::ksadj::region_kernel<1, true, false>
                                       : swept::ksadj::region_kernel<1, true, true>);
-      hipLaunchKernelGGL(kern, dim3((unsigned)(a->batch * a->nt)), dim3(kW), 0, st, ur, nullptr, ck_in, nullptr,
+      hipLaunchKernelGGL(kern, dim3((unsigned)a->nt, (unsigned)a->batch), dim3(kW), 0, st, ur, nullptr, ck_in, nullptr,
                          static_cast<const double*>(g_uT), a->lam_slots, lam_r, a->k, a->c, a->n, a->nt, p);
       e = hipGetLastError();
     }

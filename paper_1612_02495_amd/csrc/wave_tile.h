@@ -56,6 +56,20 @@ __device__ __forceinline__ T pick(bool c, T a, T b) {
   return c ? a : b;
 }
 
+// Lanes [lo, hi) of a wave64 as a 64-bit lane mask (bit i = lane i), clipped
+// to the wave.  With compile-time bounds this folds to a constant.
+__host__ __device__ constexpr uint64_t range_bits(int lo, int hi) {
+  lo = lo < 0 ? 0 : lo;
+  hi = hi > 64 ? 64 : hi;
+  if (hi <= lo) return 0;
+  const uint64_t below_hi = hi >= 64 ? ~0ull : ((1ull << hi) - 1);
+  return below_hi & ~((1ull << lo) - 1);
+}
+
+// This lane's bit of a wave-uniform lane mask.  A constant mask becomes a
+// scalar operand of the select itself: no per-lane compare is issued.
+__device__ __forceinline__ bool lanes(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
 // Halo values of lane L's neighbours: lo[i] = point L*P - S + i, hi[i] =
 // point L*P + P + i.  With TIPS, lane 0's lo and lane (kE-1)'s hi are the
 // triangle tips beyond the tile ends.

@@ -8,6 +8,7 @@ from paper_1612_02495_amd import _lib
 
 @pytest.mark.parametrize("args,code", [
     ((0, 1024, 1, 1e-6, 1e-3, 100), _lib.SWEPT_EINVAL),        # batch
+    ((65536, 1024, 1, 1e-6, 1e-3, 100), _lib.SWEPT_EINVAL),    # batch beyond one grid dimension
     ((2, 1000, 1, 1e-6, 1e-3, 100), _lib.SWEPT_EUNSUPPORTED),  # n not a multiple of 64
     ((2, 1024, 0, 1e-6, 1e-3, 100), _lib.SWEPT_EUNSUPPORTED),  # f32
     ((2, 1024, 1, 1e-6, 1e-3, 0), _lib.SWEPT_EINVAL),          # steps
@@ -29,6 +30,7 @@ def test_adjoint_null_handles():
 
 @pytest.mark.parametrize("args,code", [
     ((0, 1024, 1, 0.005, 0.5, 100), _lib.SWEPT_EINVAL),        # batch
+    ((65536, 1024, 1, 0.005, 0.5, 100), _lib.SWEPT_EINVAL),    # batch beyond one grid dimension
     ((1, 1000, 1, 0.005, 0.5, 100), _lib.SWEPT_EUNSUPPORTED),  # n not a multiple of 64
     ((1, 32, 1, 0.005, 0.5, 100), _lib.SWEPT_EUNSUPPORTED),    # n below one tile
     ((1, 1024, 0, 0.005, 0.5, 100), _lib.SWEPT_EUNSUPPORTED),  # f32
