@@ -246,7 +246,7 @@ def run_batch(args, wl):
     n = np.array([p.n for p in probs])
     b = Batch(n, wl["kind"], wl["dtype"], [p.dt for p in probs], [p.dx for p in probs],
               [p.alpha for p in probs], T)
-    engine = "compact" if args.engine == "auto" else args.engine  # the batch's AUTO is the compacted engine
+    engine = args.engine  # AUTO: resident kernels for small KS grids, compacted swept tiles otherwise
     b.set_engine(engine)
     u = torch.tensor(np.concatenate([p.u0 for p in probs]), device="cuda")
     for _ in range(args.warmup):
@@ -378,7 +378,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=5, help="timed bench steps (swept runs)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="heat", choices=sorted(WORKLOADS))
-    ap.add_argument("--engine", default="auto", choices=["auto", "lds", "wave", "compact"])
+    ap.add_argument("--engine", default="auto", choices=["auto", "lds", "wave", "compact", "resident"],
+                    help="phase engine; 'resident' is for the batched workloads only")
     ap.add_argument("--tile", type=int, default=0,
                     help="tile width (0 = run the autotuner and use its choice)")
     ap.add_argument("--horizon", type=int, default=0, help="timesteps per run (0 = workload default)")

@@ -81,6 +81,9 @@ extern "C" {
 #define SWEPT_ENGINE_COMPACT 3 /* wave64 per tile, V/Lambda compacted onto the
                                   lanes: R points per lane as the part grows or
                                   shrinks, bands in LDS                         */
+#define SWEPT_ENGINE_RESIDENT 4 /* batched runs only: grids of at most 16384
+                                   points whole in one workgroup's registers,
+                                   the rest as compacted tiles                 */
 
 typedef struct swept_plan_s* swept_plan;
 
@@ -233,37 +236,49 @@ typedef struct swept_batch_s* swept_batch;
  *                        for heat only and may be NULL for KS); constants are
  *                        formed as in swept_plan_create
  * The grids live back to back in one device array in input order (offsets
- * from swept_batch_info).  Every grid is run with the swept rule of
- * swept_run: wave-resident tiles of at most 64 P points (P = 8 points per
- * lane for heat on the compacted engine, 16 otherwise) with two halves of
- * equal or neighbouring whole-lane widths (uneven tiles, flattened phases on
- * the wider halves), zig-zag tilings, edge bands through HBM (Sec. 4.2-4.3).
- * One persistent kernel runs the whole batch: each workgroup pulls the next
- * grid, largest first, from a device counter and advances it through all of
- * its phases.  The plan owns the edge slots, the grid descriptors and the
- * counter.  Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE.
+ * from swept_batch_info).  With the RESIDENT engine (the default for KS),
+ * every grid of at most 16384 points runs whole in one workgroup of 1, 4 or
+ * 16 waves, 16 points per lane held in registers for all the steps, halos
+ * passed between lanes and waves each sub-step: a single tile whose phase is
+ * the whole run, with no edge band through HBM; these workgroups run beside
+ * the persistent kernel.  Every other grid (every grid with the COMPACT or
+ * WAVE engine, and with AUTO for heat) is run with the swept rule of
+ * swept_run: wave-resident tiles
+ * of at most 64 P points (P = 8 points per lane for heat on the compacted
+ * engine, 16 otherwise) with two halves of equal or neighbouring whole-lane
+ * widths (uneven tiles, flattened phases on the wider halves), zig-zag
+ * tilings, edge bands through HBM (Sec. 4.2-4.3), by one persistent kernel:
+ * each workgroup pulls the next grid, largest first, from a device counter
+ * and advances it through all of its phases.  The plan owns the edge slots,
+ * the grid descriptors and the counter.  Errors: EINVAL, EUNSUPPORTED,
+ * ENOMEM, EDEVICE.
  */
 int swept_batch_create(swept_batch* out, int32_t nprob, const int64_t* n, int kind, int dtype, const double* dt,
                        const double* dx, const double* alpha, int64_t steps);
 
 /*
  * swept_batch_run -- advance every grid of u (device, sum n[i] elements,
- * in/out) by the plan's steps.  use_graph != 0: the counter reset and the
- * persistent kernel are captured once into a HIP graph (re-captured when u
- * changes) and replayed with one graph launch; use_graph == 0: the same two
- * launches enqueued directly.  Asynchronous on `stream`.  Results equal
+ * in/out) by the plan's steps.  use_graph != 0: the whole-grid kernel, the
+ * counter reset and the persistent kernel are captured once into a HIP graph
+ * (re-captured when u changes) and replayed with one graph launch;
+ * use_graph == 0: the same launches enqueued directly.  Asynchronous on `stream`.  Results equal
  * naive_run / swept_run of each grid on its own, bit for bit.
  */
 int swept_batch_run(swept_batch b, void* u, int use_graph, void* stream);
 
 /*
- * swept_batch_set_engine -- choose the per-tile algorithm of the persistent
- * kernel: SWEPT_ENGINE_AUTO or SWEPT_ENGINE_COMPACT (compacted layouts, edge
- * bands in LDS; the default) or SWEPT_ENGINE_WAVE (register engine, every
- * tier over the whole tile).  Both give the same values bit for bit and leave
- * the same edge slots.  Changing the engine re-sizes the persistent grid
- * (the engines need different LDS) and drops a captured graph, so call it
- * between runs, never while one is in flight.  SWEPT_ENGINE_LDS fails with
+ * swept_batch_set_engine -- choose how the grids run: SWEPT_ENGINE_RESIDENT
+ * (grids of at most 16384 points whole in the register-resident kernels, the
+ * rest as compacted swept tiles), SWEPT_ENGINE_COMPACT (every grid as
+ * compacted swept tiles: compacted layouts, edge bands in LDS),
+ * SWEPT_ENGINE_WAVE (every grid as register-engine swept tiles, every tier
+ * over the whole tile) or SWEPT_ENGINE_AUTO (the default: RESIDENT for KS,
+ * COMPACT for heat -- measured on the 4096-grid workloads, where for heat the
+ * persistent kernel's tail absorbs the small grids at less cost than a
+ * second kernel beside it).  All give the same values bit for bit.  Changing the
+ * engine rebuilds the grid descriptors and edge slots, re-sizes the
+ * persistent grid (the engines need different LDS) and drops a captured
+ * graph, so call it between runs, never while one is in flight.  SWEPT_ENGINE_LDS fails with
  * EUNSUPPORTED, other values with EINVAL; on failure the plan keeps its
  * engine.
  */

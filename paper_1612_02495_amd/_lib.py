@@ -28,6 +28,7 @@ SWEPT_ENGINE_AUTO = 0
 SWEPT_ENGINE_LDS = 1
 SWEPT_ENGINE_WAVE = 2
 SWEPT_ENGINE_COMPACT = 3
+SWEPT_ENGINE_RESIDENT = 4
 
 _lock = threading.Lock()
 _lib = None

@@ -104,6 +104,121 @@ batch_kernel(const BatchItem<T>* __restrict__ items, int nitems, T* u, T* slots,
   }
 }
 
+// Whole-grid kernel for the grids that fit one workgroup's registers
+// (n <= kResMax): one workgroup per grid, lane g of its NW waves holding
+// points [16 g, 16 g + 16) of the ring for all the steps.  Grids come in
+// three classes by size, each with its own workgroup size (1, 4 or 16
+// waves), so a small grid does not hold a whole CU's registers.  A grid this small
+// needs no decomposition in time: every sub-step updates every point, so no
+// lane idles on a triangle and no edge band is selected or stored; only the
+// halos move -- by lane shifts inside a wave, and through a small LDS
+// exchange (double-buffered by sub-step parity, one workgroup barrier per
+// sub-step) between waves and across the periodic seam.  Each point gets the
+// same update in the same order as in every other engine, so the results are
+// the naive run's bit for bit.
+constexpr int kResQ = 16;                // points per lane
+constexpr int kResWaves[3] = {16, 4, 1};  // waves per workgroup of each size class
+constexpr int kResMax = kResQ * 64 * 16;  // 16384 points
+
+// Size class of a resident grid: the smallest workgroup that holds it.
+__host__ __device__ constexpr int res_class(int64_t n) { return n > kResQ * 64 * 4 ? 0 : (n > kResQ * 64 ? 1 : 2); }
+
+template <int KIND, typename T, int NW>
+__global__ void __launch_bounds__(64 * NW)
+resident_kernel(const BatchItem<T>* __restrict__ items, T* u, int64_t steps) {
+  constexpr int S = Radius<KIND>::value;
+  constexpr int Q = kResQ;
+  __shared__ T edF[2][NW][S];  // per wave: the first S points of its lane 0
+  __shared__ T edL[2][NW][S];  // per wave: the last S points of its lane 63
+  __shared__ T edC[2][S];      // the last S points of the ring (lane c-1)
+  const BatchItem<T> pr = items[blockIdx.x];
+  const int g = threadIdx.x;
+  const int lane = g & 63;
+  const int wv = g >> 6;
+  const int c = pr.n / Q;             // lanes holding points
+  const bool busy = wv * 64 < c;      // wave-uniform: the wave holds points
+  const bool active = g < c;
+  // halos that do not come from the neighbouring lane of the same wave
+  const bool first = active && lane == 0;
+  const bool last = active && (lane == 63 || g == c - 1);
+  T* ring = u + pr.u_off;
+  T A[Q], B[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) A[i] = active ? ring[(int64_t)g * Q + i] : T(0);
+  int sub = 0;
+  // Publish this lane's edge points, then gather the halos of src.
+  auto exchange = [&](const T (&src)[Q], T (&lo)[S], T (&hi)[S]) {
+    const int bf = sub & 1;
+    if (busy) {
+      if (active && lane == 0)
+#pragma unroll
+        for (int i = 0; i < S; ++i) edF[bf][wv][i] = src[i];
+      if (active && lane == 63)
+#pragma unroll
+        for (int i = 0; i < S; ++i) edL[bf][wv][i] = src[Q - S + i];
+      if (g == c - 1)
+#pragma unroll
+        for (int i = 0; i < S; ++i) edC[bf][i] = src[Q - S + i];
+    }
+    __syncthreads();
+    T xl[S] = {}, xr[S] = {};
+    if (first) {
+#pragma unroll
+      for (int i = 0; i < S; ++i) xl[i] = g == 0 ? edC[bf][i] : edL[bf][wv - 1][i];
+    }
+    if (last) {
+#pragma unroll
+      for (int i = 0; i < S; ++i) xr[i] = g == c - 1 ? edF[bf][0][i] : edF[bf][wv + 1][i];
+    }
+    wave::halos<T, Q, S, true>(src, xl, xr, first, last, lo, hi);
+    ++sub;
+  };
+  const Consts<T> k = pr.k;
+  if constexpr (KIND == kHeat) {
+    // two steps per iteration, A -> B -> A, so no register moves back
+    auto step = [&](const T (&src)[Q], T (&dst)[Q]) {
+      T lo[S], hi[S];
+      exchange(src, lo, hi);
+      if (busy) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          dst[i] = heat_update(i > 0 ? src[i - 1] : lo[0], src[i], i + 1 < Q ? src[i + 1] : hi[0], k);
+      }
+    };
+    for (int64_t s = 0; s + 1 < steps; s += 2) {
+      step(A, B);
+      step(B, A);
+    }
+    if (steps & 1) {
+      step(A, B);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) A[i] = B[i];
+    }
+  } else {
+    for (int64_t s = 0; s < steps; ++s) {
+      T lo[S], hi[S];
+      exchange(A, lo, hi);
+      if (busy) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          B[i] = ks_predictor(wave::at<T, Q, S>(A, lo, hi, i - 2), wave::at<T, Q, S>(A, lo, hi, i - 1), A[i],
+                              wave::at<T, Q, S>(A, lo, hi, i + 1), wave::at<T, Q, S>(A, lo, hi, i + 2), k);
+      }
+      exchange(B, lo, hi);
+      if (busy) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          A[i] = ks_final(A[i], wave::at<T, Q, S>(B, lo, hi, i - 2), wave::at<T, Q, S>(B, lo, hi, i - 1), B[i],
+                          wave::at<T, Q, S>(B, lo, hi, i + 1), wave::at<T, Q, S>(B, lo, hi, i + 2), k);
+      }
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) ring[(int64_t)g * Q + i] = A[i];
+  }
+}
+
 }  // namespace
 }  // namespace swept
 
@@ -126,7 +241,11 @@ struct swept_batch_s {
   std::vector<double> dt, dx, alpha;
   std::vector<int32_t> order;  // queue order: largest first
   int P = 16;                  // points per lane of the current tiling
-  void* items = nullptr;       // device BatchItem<T>[nprob], queue order
+  int32_t nswept = 0;          // grids run by the persistent swept kernel
+  int32_t nres = 0;            // grids run whole by the resident kernels (AUTO engine)
+  int32_t res_count[3] = {};   // resident grids per size class (16, 4, 1 waves)
+  void* items = nullptr;       // device BatchItem<T>[nswept], queue order
+  void* res_items = nullptr;   // device BatchItem<T>[nres], largest first (so by class)
   void* slots = nullptr;
   size_t slots_bytes = 0;
   int* queue = nullptr;
@@ -134,6 +253,8 @@ struct swept_batch_s {
   int engine = SWEPT_ENGINE_AUTO;  // AUTO runs the compacted engine
   int grid = 0;
   hipStream_t cap_stream = nullptr;
+  hipStream_t side = nullptr;      // the resident kernels' branch, beside the persistent kernel
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   void* graph_u = nullptr;
@@ -173,8 +294,30 @@ void* kernel_for(const swept_batch_s* b) {
 template <int KIND, typename T, int P, int C>
 void launch_batch(const swept_batch_s* b, void* u, int64_t tiers, hipStream_t st) {
   hipLaunchKernelGGL((swept::batch_kernel<KIND, T, P, swept::kBatchNW, C>), dim3((unsigned)b->grid),
-                     dim3(64 * swept::kBatchNW), 0, st, static_cast<const BatchItem<T>*>(b->items), b->nprob,
+                     dim3(64 * swept::kBatchNW), 0, st, static_cast<const BatchItem<T>*>(b->items), b->nswept,
                      static_cast<T*>(u), static_cast<T*>(b->slots), tiers, b->queue);
+}
+
+template <int KIND, typename T>
+void launch_resident(const swept_batch_s* b, void* u, hipStream_t st) {
+  const auto* items = static_cast<const BatchItem<T>*>(b->res_items);
+  int32_t first = 0;
+  for (int cl = 0; cl < 3; ++cl) {
+    const int32_t cnt = b->res_count[cl];
+    if (cnt > 0) {
+      const dim3 grid((unsigned)cnt), block((unsigned)(64 * swept::kResWaves[cl]));
+      if (cl == 0)
+        hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[0]>), grid, block, 0, st, items + first,
+                           static_cast<T*>(u), b->steps);
+      else if (cl == 1)
+        hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[1]>), grid, block, 0, st, items + first,
+                           static_cast<T*>(u), b->steps);
+      else
+        hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[2]>), grid, block, 0, st, items + first,
+                           static_cast<T*>(u), b->steps);
+    }
+    first += cnt;
+  }
 }
 
 template <int P, int C>
@@ -192,7 +335,54 @@ void launch_batch_pc(const swept_batch_s* b, void* u, int64_t tiers, hipStream_t
   }
 }
 
+hipError_t launch_resident_all(swept_batch_s* b, void* u, hipStream_t st) {
+  if (b->kind == SWEPT_HEAT_FTCS) {
+    if (b->dtype == SWEPT_F64)
+      launch_resident<swept::kHeat, double>(b, u, st);
+    else
+      launch_resident<swept::kHeat, float>(b, u, st);
+  } else {
+    if (b->dtype == SWEPT_F64)
+      launch_resident<swept::kKS, double>(b, u, st);
+    else
+      launch_resident<swept::kKS, float>(b, u, st);
+  }
+  return hipGetLastError();
+}
+
+// Stream and events of the side branch, made on first use.
+hipError_t ensure_side(swept_batch_s* b) {
+  hipError_t e = hipSuccess;
+  if (!b->side) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+  if (e == hipSuccess && !b->ev_fork) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess && !b->ev_join) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+  return e;
+}
+
+hipError_t launch_swept(swept_batch_s* b, void* u, hipStream_t st);
+
+// The resident grids and the swept grids are independent, so their kernels
+// run side by side: the resident launches go on a side stream forked from
+// and joined back to `st` by events (captured as a parallel branch of the
+// graph), and the small grids fill the CUs around the persistent kernel's
+// workgroups instead of running before them.
 hipError_t enqueue_batch(swept_batch_s* b, void* u, hipStream_t st) {
+  if (b->nres > 0 && b->nswept > 0) {
+    hipError_t e = ensure_side(b);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
+    if (e == hipSuccess) e = launch_resident_all(b, u, b->side);
+    if (e == hipSuccess) e = launch_swept(b, u, st);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join, 0);
+    return e;
+  }
+  if (b->nres > 0) return launch_resident_all(b, u, st);
+  return launch_swept(b, u, st);
+}
+
+hipError_t launch_swept(swept_batch_s* b, void* u, hipStream_t st) {
+  if (b->nswept == 0) return hipSuccess;
   hipLaunchKernelGGL(swept::batch_reset_kernel, dim3(1), dim3(1), 0, st, b->queue);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -219,7 +409,7 @@ hipError_t size_grid(swept_batch_s* b) {
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
-  b->grid = (int)std::min<int64_t>((int64_t)per_cu * cus, b->nprob);
+  b->grid = (int)std::min<int64_t>((int64_t)per_cu * cus, b->nswept);
   return hipSuccess;
 }
 
@@ -247,16 +437,48 @@ Consts<T> consts_for(double dt, double dx, double alpha) {
   return k;
 }
 
-// Grid descriptors of the tiling with P points per lane, in queue order.
+// Whether the grids that fit one workgroup's registers run whole in the
+// resident kernels: with the RESIDENT engine, and with AUTO for KS.  For heat
+// AUTO keeps them in the persistent kernel's queue, where they fill its tail
+// (measured on the 4096-grid workload: 70.7 ms that way against 75.9 ms with
+// the resident kernels beside it, whose 16-wave workgroups wait for free
+// CUs; KS: 475.6 ms against 435.7 ms in the resident kernels).
+bool resident_engine(int kind, int engine) {
+  return engine == SWEPT_ENGINE_RESIDENT || (engine == SWEPT_ENGINE_AUTO && kind == SWEPT_KS_RK2);
+}
+
+// Whether grid i runs whole in the resident kernels.
+bool resident(const swept_batch_s* b, int engine, int32_t i) {
+  return resident_engine(b->kind, engine) && b->n[(size_t)i] <= swept::kResMax;
+}
+
+// Descriptors of the resident grids (largest first; no slots).
 template <typename T>
-std::vector<BatchItem<T>> make_items(const swept_batch_s* b, int P, size_t* slot_values) {
+std::vector<BatchItem<T>> make_res_items(const swept_batch_s* b, int engine) {
+  std::vector<BatchItem<T>> items;
+  for (int32_t i : b->order) {
+    if (!resident(b, engine, i)) continue;
+    BatchItem<T> it{};
+    it.u_off = b->offsets[(size_t)i];
+    it.n = (int32_t)b->n[(size_t)i];
+    it.k = consts_for<T>(b->dt[(size_t)i], b->dx[(size_t)i], b->kind == SWEPT_HEAT_FTCS ? b->alpha[(size_t)i] : 0.0);
+    items.push_back(it);
+  }
+  return items;
+}
+
+// Grid descriptors of the swept grids' tiling with P points per lane, in
+// queue order.
+template <typename T>
+std::vector<BatchItem<T>> make_items(const swept_batch_s* b, int engine, int P, size_t* slot_values) {
   const int S = b->kind == SWEPT_KS_RK2 ? 2 : 1;
   const int64_t slen = 64 * P + 2 * S;
-  std::vector<BatchItem<T>> items((size_t)b->nprob);
+  std::vector<BatchItem<T>> items;
   int64_t soff = 0;
-  for (int32_t q = 0; q < b->nprob; ++q) {
-    const int32_t i = b->order[(size_t)q];
-    BatchItem<T>& it = items[(size_t)q];
+  for (int32_t i : b->order) {
+    if (resident(b, engine, i)) continue;
+    items.emplace_back();
+    BatchItem<T>& it = items.back();
     const int c = (int)(b->n[(size_t)i] / P);
     it.u_off = b->offsets[(size_t)i];
     it.slot_off = soff;
@@ -274,42 +496,71 @@ std::vector<BatchItem<T>> make_items(const swept_batch_s* b, int P, size_t* slot
   return items;
 }
 
-// (Re)build the device descriptors and edge slots for P points per lane.
-// On failure the plan keeps its previous tiling.
-int build_tiling(swept_batch_s* b, int P) {
-  size_t slot_values = 0, item_bytes = 0;
+// Upload host bytes to a new device buffer (at least 8 bytes).
+hipError_t upload(void** out, const void* host, size_t bytes) {
+  *out = nullptr;
+  hipError_t e = hipMalloc(out, std::max<size_t>(bytes, 8));
+  if (e == hipSuccess && bytes) e = hipMemcpy(*out, host, bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess && *out) {
+    (void)hipFree(*out);
+    *out = nullptr;
+  }
+  return e;
+}
+
+// (Re)build the device descriptors of both kernels and the edge slots of the
+// swept grids for an engine and P points per lane.  On failure the plan
+// keeps its previous tiling.
+int build_tiling(swept_batch_s* b, int engine, int P) {
+  size_t slot_values = 0, item_bytes = 0, res_bytes = 0;
   const void* host_items = nullptr;
-  std::vector<BatchItem<double>> id;
-  std::vector<BatchItem<float>> ifl;
+  const void* host_res = nullptr;
+  std::vector<BatchItem<double>> id, rd;
+  std::vector<BatchItem<float>> ifl, rf;
+  size_t nsw = 0, nre = 0;
   if (b->dtype == SWEPT_F64) {
-    id = make_items<double>(b, P, &slot_values);
+    id = make_items<double>(b, engine, P, &slot_values);
+    rd = make_res_items<double>(b, engine);
     host_items = id.data();
-    item_bytes = id.size() * sizeof(BatchItem<double>);
+    host_res = rd.data();
+    nsw = id.size();
+    nre = rd.size();
+    item_bytes = nsw * sizeof(BatchItem<double>);
+    res_bytes = nre * sizeof(BatchItem<double>);
   } else {
-    ifl = make_items<float>(b, P, &slot_values);
+    ifl = make_items<float>(b, engine, P, &slot_values);
+    rf = make_res_items<float>(b, engine);
     host_items = ifl.data();
-    item_bytes = ifl.size() * sizeof(BatchItem<float>);
+    host_res = rf.data();
+    nsw = ifl.size();
+    nre = rf.size();
+    item_bytes = nsw * sizeof(BatchItem<float>);
+    res_bytes = nre * sizeof(BatchItem<float>);
   }
   const size_t es = b->dtype == SWEPT_F64 ? sizeof(double) : sizeof(float);
   void* items = nullptr;
+  void* res = nullptr;
   void* slots = nullptr;
-  hipError_t e = hipMalloc(&items, item_bytes);
-  if (e == hipSuccess) e = hipMalloc(&slots, slot_values * es);
+  hipError_t e = upload(&items, host_items, item_bytes);
+  if (e == hipSuccess) e = upload(&res, host_res, res_bytes);
+  if (e == hipSuccess) e = hipMalloc(&slots, std::max<size_t>(slot_values * es, 8));
   if (e != hipSuccess) {
     if (items) (void)hipFree(items);
-    return bfail(SWEPT_ENOMEM, std::string("hipMalloc(batch): ") + hipGetErrorString(e));
-  }
-  e = hipMemcpy(items, host_items, item_bytes, hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    (void)hipFree(items);
-    (void)hipFree(slots);
-    return bhip(e, "hipMemcpy(batch items)");
+    if (res) (void)hipFree(res);
+    return bfail(SWEPT_ENOMEM, std::string("hipMalloc/hipMemcpy(batch): ") + hipGetErrorString(e));
   }
   if (b->items) (void)hipFree(b->items);
+  if (b->res_items) (void)hipFree(b->res_items);
   if (b->slots) (void)hipFree(b->slots);
   b->items = items;
+  b->res_items = res;
   b->slots = slots;
   b->slots_bytes = slot_values * es;
+  b->nswept = (int32_t)nsw;
+  b->nres = (int32_t)nre;
+  for (int cl = 0; cl < 3; ++cl) b->res_count[cl] = 0;
+  for (int32_t i : b->order)
+    if (resident(b, engine, i)) ++b->res_count[swept::res_class(b->n[(size_t)i])];
   b->P = P;
   return SWEPT_OK;
 }
@@ -318,7 +569,11 @@ void batch_free(swept_batch_s* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->side) (void)hipStreamDestroy(b->side);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
   if (b->items) (void)hipFree(b->items);
+  if (b->res_items) (void)hipFree(b->res_items);
   if (b->slots) (void)hipFree(b->slots);
   if (b->queue) (void)hipFree(b->queue);
   delete b;
@@ -372,7 +627,7 @@ int swept_batch_create(swept_batch* out, int32_t nprob, const int64_t* n, int ki
     delete b;
     return bhip(e, "hipGetDevice");
   }
-  int rc = build_tiling(b, points_per_lane(kind, b->engine));
+  int rc = build_tiling(b, b->engine, points_per_lane(kind, b->engine));
   if (rc != SWEPT_OK) {
     batch_free(b);
     return rc;
@@ -394,7 +649,8 @@ int swept_batch_create(swept_batch* out, int32_t nprob, const int64_t* n, int ki
 int swept_batch_set_engine(swept_batch b, int engine) {
   if (!b) return bfail(SWEPT_EINVAL, "batch must not be NULL");
   if (engine == SWEPT_ENGINE_LDS) return bfail(SWEPT_EUNSUPPORTED, "the batched kernel has no LDS engine");
-  if (engine != SWEPT_ENGINE_AUTO && engine != SWEPT_ENGINE_WAVE && engine != SWEPT_ENGINE_COMPACT)
+  if (engine != SWEPT_ENGINE_AUTO && engine != SWEPT_ENGINE_WAVE && engine != SWEPT_ENGINE_COMPACT &&
+      engine != SWEPT_ENGINE_RESIDENT)
     return bfail(SWEPT_EINVAL, "unknown engine");
   if (engine == b->engine) return SWEPT_OK;
   int prev = -1;
@@ -402,19 +658,18 @@ int swept_batch_set_engine(swept_batch b, int engine) {
   if (e == hipSuccess && prev != b->device) e = hipSetDevice(b->device);
   if (e != hipSuccess) return bhip(e, "hipSetDevice");
   const int old_engine = b->engine;
-  const int P = points_per_lane(b->kind, engine);
-  int rc = SWEPT_OK;
-  if (P != b->P) rc = build_tiling(b, P);  // the slots hold no state between runs
+  // the grids' split between the kernels and the tiling follow the engine;
+  // the slots hold no state between runs
+  int rc = build_tiling(b, engine, points_per_lane(b->kind, engine));
   if (rc == SWEPT_OK) {
     b->engine = engine;
     e = size_grid(b);
     if (e != hipSuccess) {
       b->engine = old_engine;
       rc = bhip(e, "occupancy query");
-      if (P != points_per_lane(b->kind, old_engine)) (void)build_tiling(b, points_per_lane(b->kind, old_engine));
-    } else {
-      drop_graph(b);
+      (void)build_tiling(b, old_engine, points_per_lane(b->kind, old_engine));
     }
+    drop_graph(b);
   }
   if (prev != b->device) (void)hipSetDevice(prev);
   return rc;

@@ -10,12 +10,13 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (SWEPT_ENGINE_AUTO, SWEPT_ENGINE_COMPACT, SWEPT_ENGINE_LDS, SWEPT_ENGINE_WAVE, SWEPT_F32, SWEPT_F64,
-                   SWEPT_HEAT_FTCS, SWEPT_HEAT_INSULATED, SWEPT_KS_RK2, SweptError, check)
+from ._lib import (SWEPT_ENGINE_AUTO, SWEPT_ENGINE_COMPACT, SWEPT_ENGINE_LDS, SWEPT_ENGINE_RESIDENT,
+                   SWEPT_ENGINE_WAVE, SWEPT_F32, SWEPT_F64, SWEPT_HEAT_FTCS, SWEPT_HEAT_INSULATED,
+                   SWEPT_KS_RK2, SweptError, check)
 
 KINDS = {"heat": SWEPT_HEAT_FTCS, "ks": SWEPT_KS_RK2, "heat_insulated": SWEPT_HEAT_INSULATED}
 ENGINES = {"auto": SWEPT_ENGINE_AUTO, "lds": SWEPT_ENGINE_LDS, "wave": SWEPT_ENGINE_WAVE,
-           "compact": SWEPT_ENGINE_COMPACT}
+           "compact": SWEPT_ENGINE_COMPACT, "resident": SWEPT_ENGINE_RESIDENT}
 
 
 def _kind(kind) -> int:
@@ -187,7 +188,10 @@ class Batch:
         self.workspace_bytes = inf["workspace_bytes"]
 
     def set_engine(self, engine):
-        """'auto' / 'compact' (compacted layouts) or 'wave' (register engine)."""
+        """'resident' (grids of up to 16384 points whole in one workgroup's
+        registers, the rest as compacted swept tiles), 'compact' (compacted swept
+        tiles for every grid), 'wave' (register-engine swept tiles for every
+        grid) or 'auto' ('resident' for KS, 'compact' for heat)."""
         swept_batch_set_engine(self._h, engine)
         self.grid = swept_batch_info(self._h, self.n.size)["grid"]
         return self

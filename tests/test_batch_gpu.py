@@ -1,6 +1,8 @@
-"""Batched persistent kernel on the GPU: every grid of the batch equals its
-own naive run (and the oracle) bit for bit with either per-tile engine
-(compacted layouts or register engine); graph replays equal eager runs."""
+"""Batched kernels on the GPU: every grid of the batch equals its own naive
+run (and the oracle) bit for bit with every engine -- RESIDENT (grids of up
+to 16384 points whole in one workgroup's registers, beside compacted swept
+tiles for the rest), compacted tiles for all, register-engine tiles for all,
+and AUTO; graph replays equal eager runs."""
 import numpy as np
 import pytest
 
@@ -13,8 +15,11 @@ pytestmark = pytest.mark.gpu
 
 def _sizes(seed, m):
     rng = np.random.default_rng(seed)
-    # uneven halves, one-tile rings, multi-tile rings, the 2^16 maximum
-    base = [32, 48, 256, 272, 1008, 1024, 1040, 2064, 4096, 5008, 65536]
+    # uneven halves, one-tile rings, multi-tile rings, the 2^16 maximum; for
+    # the whole-grid kernel: 2 and 3 lanes, exactly one wave (1024), one lane
+    # into a second wave (1040), all 16 waves (16384) and the first size
+    # beyond it (16400, swept)
+    base = [32, 48, 256, 272, 1008, 1024, 1040, 2064, 4096, 5008, 16384, 16400, 65536]
     extra = list(16 * rng.integers(2, 700, size=m - len(base)))
     return np.array(base + extra, dtype=np.int64)
 
@@ -34,7 +39,7 @@ def _batch_case(kind, dtype, steps, seed=0, m=40):
     return n, dt, dx, alpha, u0
 
 
-@pytest.mark.parametrize("engine", ["compact", "wave"])
+@pytest.mark.parametrize("engine", ["auto", "resident", "compact", "wave"])
 @pytest.mark.parametrize("kind,dtype,steps", [("heat", torch.float64, 300), ("heat", torch.float32, 129),
                                               ("ks", torch.float64, 61), ("ks", torch.float32, 40)])
 def test_batch_equals_per_grid_naive_and_oracle(kind, dtype, steps, engine):
@@ -58,7 +63,7 @@ def test_batch_equals_per_grid_naive_and_oracle(kind, dtype, steps, engine):
             assert np.array_equal(parts[i], ref), f"grid {i} (n={n[i]}) differs from the oracle"
 
 
-@pytest.mark.parametrize("engine", ["compact", "wave"])
+@pytest.mark.parametrize("engine", ["auto", "resident", "compact", "wave"])
 def test_batch_graph_replays_match_eager(engine):
     n, dt, dx, alpha, u0 = _batch_case("heat", torch.float64, 200, seed=5, m=24)
     b = Batch(n, "heat", torch.float64, dt, dx, alpha, 200).set_engine(engine)
@@ -111,12 +116,12 @@ def test_batch_engines_agree_and_switch(kind):
     b = Batch(n, kind, torch.float64, dt, dx, alpha, 33)
     x = torch.tensor(np.concatenate(u0), device="cuda")
     y = x.clone()
-    b.run(x)                      # default: compacted, graph
-    b.set_engine("wave").run(y)   # register engine: the graph is re-captured
+    b.run(x)                      # default (AUTO), graph
+    b.set_engine("wave").run(y)   # register engine for every grid: the graph is re-captured
     torch.cuda.synchronize()
     assert torch.equal(x, y)
     b.set_engine("compact").run(y, use_graph=False)
-    b.run(x, use_graph=False)
+    b.set_engine("resident").run(x, use_graph=False)
     torch.cuda.synchronize()
     assert torch.equal(x, y)
     with pytest.raises(Exception):
