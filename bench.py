@@ -246,7 +246,7 @@ def run_batch(args, wl):
     n = np.array([p.n for p in probs])
     b = Batch(n, wl["kind"], wl["dtype"], [p.dt for p in probs], [p.dx for p in probs],
               [p.alpha for p in probs], T)
-    engine = args.engine  # AUTO: resident kernels for small KS grids, compacted swept tiles otherwise
+    engine = args.engine  # AUTO: small grids whole in the resident kernels, the rest compacted swept tiles
     b.set_engine(engine)
     u = torch.tensor(np.concatenate([p.u0 for p in probs]), device="cuda")
     for _ in range(args.warmup):
@@ -260,7 +260,7 @@ def run_batch(args, wl):
     if not args.no_cpu_baseline:
         import time as _time
         import oracle
-        budget = args.cpu_steps or 200
+        budget = min(T, args.cpu_steps or (5000 if wl["kind"] == "heat" else 1000))
         big = max(probs, key=lambda p: p.n)
         t0 = _time.perf_counter()
         for p in probs[:64]:

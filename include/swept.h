@@ -236,15 +236,15 @@ typedef struct swept_batch_s* swept_batch;
  *                        for heat only and may be NULL for KS); constants are
  *                        formed as in swept_plan_create
  * The grids live back to back in one device array in input order (offsets
- * from swept_batch_info).  With the RESIDENT engine (the default for KS),
- * every grid of at most 16384 points runs whole in one workgroup of 1, 4 or
- * 16 waves, 16 points per lane held in registers for all the steps, halos
- * passed between lanes and waves each sub-step: a single tile whose phase is
- * the whole run, with no edge band through HBM; these workgroups run beside
- * the persistent kernel.  Every other grid (every grid with the COMPACT or
- * WAVE engine, and with AUTO for heat) is run with the swept rule of
- * swept_run: wave-resident tiles
- * of at most 64 P points (P = 8 points per lane for heat on the compacted
+ * from swept_batch_info).  With the default engine (AUTO, the same as
+ * RESIDENT), every grid of at most 16384 points runs whole in one workgroup
+ * of 1, 4 or 16 waves, 16 points per lane held in registers for all the
+ * steps, halos passed between lanes and waves each sub-step: a single tile
+ * whose phase is the whole run, with no edge band through HBM; these
+ * workgroups run beside the persistent kernel.  Every other grid (every grid
+ * with the COMPACT or WAVE engine) is run with the swept rule of swept_run:
+ * wave-resident tiles
+ * of at most 64 P points (P = 8 points per lane for heat with the COMPACT
  * engine, 16 otherwise) with two halves of equal or neighbouring whole-lane
  * widths (uneven tiles, flattened phases on the wider halves), zig-zag
  * tilings, edge bands through HBM (Sec. 4.2-4.3), by one persistent kernel:
@@ -272,10 +272,9 @@ int swept_batch_run(swept_batch b, void* u, int use_graph, void* stream);
  * rest as compacted swept tiles), SWEPT_ENGINE_COMPACT (every grid as
  * compacted swept tiles: compacted layouts, edge bands in LDS),
  * SWEPT_ENGINE_WAVE (every grid as register-engine swept tiles, every tier
- * over the whole tile) or SWEPT_ENGINE_AUTO (the default: RESIDENT for KS,
- * COMPACT for heat -- measured on the 4096-grid workloads, where for heat the
- * persistent kernel's tail absorbs the small grids at less cost than a
- * second kernel beside it).  All give the same values bit for bit.  Changing the
+ * over the whole tile) or SWEPT_ENGINE_AUTO (the default, the same as
+ * RESIDENT: measured fastest on the 4096-grid heat and KS workloads).  All
+ * give the same values bit for bit.  Changing the
  * engine rebuilds the grid descriptors and edge slots, re-sizes the
  * persistent grid (the engines need different LDS) and drops a captured
  * graph, so call it between runs, never while one is in flight.  SWEPT_ENGINE_LDS fails with

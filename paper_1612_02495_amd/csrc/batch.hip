@@ -264,13 +264,16 @@ namespace {
 
 bool compact_engine(int engine) { return engine != SWEPT_ENGINE_WAVE; }
 
-// Points per lane of the tiling an engine runs: the compacted heat tiles
-// take 8 (half the LDS and registers per wave, so three workgroups share a
-// CU), everything else 16 (measured best on MI355X for the 4096-grid
-// workloads: compacted heat 3.84e12 at 8 vs 3.17e12 at 16 cell-updates/s,
-// compacted KS 5.02e11 at 16 vs 4.75e11 at 8, register heat 3.02e12 at 16
-// vs 2.70e12 at 8).
-int points_per_lane(int kind, int engine) { return compact_engine(engine) && kind == SWEPT_HEAT_FTCS ? 8 : 16; }
+// Points per lane of the swept tiling an engine runs.  With every grid in
+// the persistent kernel (COMPACT), heat takes 8: half the LDS and registers
+// per wave, so three workgroups share a CU and the many small grids keep it
+// busy (measured on the 4096-grid workload: 3.84e12 at 8 vs 3.17e12 at 16
+// cell-updates/s).  Everything else takes 16 -- with AUTO and RESIDENT the
+// small grids run in the resident kernels, and the large ones gain from the
+// wider tiles (grids above 16384 points: 3.82e12 at 16 vs 3.03e12 at 8);
+// KS 5.02e11 at 16 vs 4.75e11 at 8; register heat 3.02e12 at 16 vs 2.70e12
+// at 8.
+int points_per_lane(int kind, int engine) { return engine == SWEPT_ENGINE_COMPACT && kind == SWEPT_HEAT_FTCS ? 8 : 16; }
 
 template <int KIND, typename T, int P, int C>
 void* batch_kernel_ptr() {
@@ -437,19 +440,22 @@ Consts<T> consts_for(double dt, double dx, double alpha) {
   return k;
 }
 
-// Whether the grids that fit one workgroup's registers run whole in the
-// resident kernels: with the RESIDENT engine, and with AUTO for KS.  For heat
-// AUTO keeps them in the persistent kernel's queue, where they fill its tail
-// (measured on the 4096-grid workload: 70.7 ms that way against 75.9 ms with
-// the resident kernels beside it, whose 16-wave workgroups wait for free
-// CUs; KS: 475.6 ms against 435.7 ms in the resident kernels).
-bool resident_engine(int kind, int engine) {
-  return engine == SWEPT_ENGINE_RESIDENT || (engine == SWEPT_ENGINE_AUTO && kind == SWEPT_KS_RK2);
+// Largest grid an engine runs whole in the resident kernels (0: none): with
+// AUTO and RESIDENT, every grid that fits one workgroup's registers.  Their
+// workgroups run beside the persistent kernel, whose P = 16 workgroups (one
+// per CU) leave room for them.  Measured on the 4096-grid heat workload:
+// 63.7 ms, against 65.1 ms with only the 1- and 4-wave classes resident and
+// 71.1 ms with every grid as P = 8 compacted tiles (which in turn beat the
+// resident kernels beside P = 8 tiles, 70.7 against 75.9 ms: the 16-wave
+// workgroups then waited for free CUs).  KS: 434 ms against 475 ms.
+int64_t resident_max(int kind, int engine) {
+  (void)kind;
+  return engine == SWEPT_ENGINE_RESIDENT || engine == SWEPT_ENGINE_AUTO ? swept::kResMax : 0;
 }
 
 // Whether grid i runs whole in the resident kernels.
 bool resident(const swept_batch_s* b, int engine, int32_t i) {
-  return resident_engine(b->kind, engine) && b->n[(size_t)i] <= swept::kResMax;
+  return b->n[(size_t)i] <= resident_max(b->kind, engine);
 }
 
 // Descriptors of the resident grids (largest first; no slots).

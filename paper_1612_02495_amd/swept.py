@@ -191,7 +191,7 @@ class Batch:
         """'resident' (grids of up to 16384 points whole in one workgroup's
         registers, the rest as compacted swept tiles), 'compact' (compacted swept
         tiles for every grid), 'wave' (register-engine swept tiles for every
-        grid) or 'auto' ('resident' for KS, 'compact' for heat)."""
+        grid) or 'auto' (the default, the same as 'resident')."""
         swept_batch_set_engine(self._h, engine)
         self.grid = swept_batch_info(self._h, self.n.size)["grid"]
         return self
