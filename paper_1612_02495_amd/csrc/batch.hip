@@ -253,8 +253,9 @@ struct swept_batch_s {
   int engine = SWEPT_ENGINE_AUTO;  // AUTO runs the compacted engine
   int grid = 0;
   hipStream_t cap_stream = nullptr;
-  hipStream_t side = nullptr;      // the resident kernels' branch, beside the persistent kernel
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t side[3] = {};        // one branch per resident size class, beside the persistent kernel
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[3] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   void* graph_u = nullptr;
@@ -301,26 +302,24 @@ void launch_batch(const swept_batch_s* b, void* u, int64_t tiers, hipStream_t st
                      static_cast<T*>(u), static_cast<T*>(b->slots), tiers, b->queue);
 }
 
+// Launch the resident grids of size class cl (0: 16 waves, 1: 4, 2: 1).
 template <int KIND, typename T>
-void launch_resident(const swept_batch_s* b, void* u, hipStream_t st) {
+void launch_resident(const swept_batch_s* b, int cl, void* u, hipStream_t st) {
   const auto* items = static_cast<const BatchItem<T>*>(b->res_items);
   int32_t first = 0;
-  for (int cl = 0; cl < 3; ++cl) {
-    const int32_t cnt = b->res_count[cl];
-    if (cnt > 0) {
-      const dim3 grid((unsigned)cnt), block((unsigned)(64 * swept::kResWaves[cl]));
-      if (cl == 0)
-        hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[0]>), grid, block, 0, st, items + first,
-                           static_cast<T*>(u), b->steps);
-      else if (cl == 1)
-        hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[1]>), grid, block, 0, st, items + first,
-                           static_cast<T*>(u), b->steps);
-      else
-        hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[2]>), grid, block, 0, st, items + first,
-                           static_cast<T*>(u), b->steps);
-    }
-    first += cnt;
-  }
+  for (int c = 0; c < cl; ++c) first += b->res_count[c];
+  const int32_t cnt = b->res_count[cl];
+  if (cnt <= 0) return;
+  const dim3 grid((unsigned)cnt), block((unsigned)(64 * swept::kResWaves[cl]));
+  if (cl == 0)
+    hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[0]>), grid, block, 0, st, items + first,
+                       static_cast<T*>(u), b->steps);
+  else if (cl == 1)
+    hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[1]>), grid, block, 0, st, items + first,
+                       static_cast<T*>(u), b->steps);
+  else
+    hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[2]>), grid, block, 0, st, items + first,
+                       static_cast<T*>(u), b->steps);
 }
 
 template <int P, int C>
@@ -338,50 +337,55 @@ void launch_batch_pc(const swept_batch_s* b, void* u, int64_t tiers, hipStream_t
   }
 }
 
-hipError_t launch_resident_all(swept_batch_s* b, void* u, hipStream_t st) {
+hipError_t launch_resident_class(swept_batch_s* b, int cl, void* u, hipStream_t st) {
   if (b->kind == SWEPT_HEAT_FTCS) {
     if (b->dtype == SWEPT_F64)
-      launch_resident<swept::kHeat, double>(b, u, st);
+      launch_resident<swept::kHeat, double>(b, cl, u, st);
     else
-      launch_resident<swept::kHeat, float>(b, u, st);
+      launch_resident<swept::kHeat, float>(b, cl, u, st);
   } else {
     if (b->dtype == SWEPT_F64)
-      launch_resident<swept::kKS, double>(b, u, st);
+      launch_resident<swept::kKS, double>(b, cl, u, st);
     else
-      launch_resident<swept::kKS, float>(b, u, st);
+      launch_resident<swept::kKS, float>(b, cl, u, st);
   }
   return hipGetLastError();
 }
 
-// Stream and events of the side branch, made on first use.
+// Streams and events of the side branches, made on first use.
 hipError_t ensure_side(swept_batch_s* b) {
   hipError_t e = hipSuccess;
-  if (!b->side) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
-  if (e == hipSuccess && !b->ev_fork) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
-  if (e == hipSuccess && !b->ev_join) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+  if (!b->ev_fork) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+  for (int cl = 0; cl < 3 && e == hipSuccess; ++cl) {
+    if (!b->side[cl]) e = hipStreamCreateWithFlags(&b->side[cl], hipStreamNonBlocking);
+    if (e == hipSuccess && !b->ev_join[cl]) e = hipEventCreateWithFlags(&b->ev_join[cl], hipEventDisableTiming);
+  }
   return e;
 }
 
 hipError_t launch_swept(swept_batch_s* b, void* u, hipStream_t st);
 
-// The resident grids and the swept grids are independent, so their kernels
-// run side by side: the resident launches go on a side stream forked from
-// and joined back to `st` by events (captured as a parallel branch of the
-// graph), and the small grids fill the CUs around the persistent kernel's
-// workgroups instead of running before them.
+// The grids are independent, so the kernels run side by side: each resident
+// size class goes on a side stream of its own, forked from and joined back
+// to `st` by events (parallel branches of the captured graph), beside the
+// persistent kernel on `st`.  Run one after another, the classes would end
+// well after the persistent kernel (heat: 65.7 ms against 52.0 ms).
 hipError_t enqueue_batch(swept_batch_s* b, void* u, hipStream_t st) {
-  if (b->nres > 0 && b->nswept > 0) {
-    hipError_t e = ensure_side(b);
-    if (e == hipSuccess) e = hipEventRecord(b->ev_fork, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
-    if (e == hipSuccess) e = launch_resident_all(b, u, b->side);
-    if (e == hipSuccess) e = launch_swept(b, u, st);
-    if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->side);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join, 0);
-    return e;
+  if (b->nres == 0) return launch_swept(b, u, st);
+  hipError_t e = ensure_side(b);
+  if (e == hipSuccess) e = hipEventRecord(b->ev_fork, st);
+  for (int cl = 0; cl < 3 && e == hipSuccess; ++cl) {
+    if (b->res_count[cl] == 0) continue;
+    e = hipStreamWaitEvent(b->side[cl], b->ev_fork, 0);
+    if (e == hipSuccess) e = launch_resident_class(b, cl, u, b->side[cl]);
   }
-  if (b->nres > 0) return launch_resident_all(b, u, st);
-  return launch_swept(b, u, st);
+  if (e == hipSuccess) e = launch_swept(b, u, st);
+  for (int cl = 0; cl < 3 && e == hipSuccess; ++cl) {
+    if (b->res_count[cl] == 0) continue;
+    e = hipEventRecord(b->ev_join[cl], b->side[cl]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join[cl], 0);
+  }
+  return e;
 }
 
 hipError_t launch_swept(swept_batch_s* b, void* u, hipStream_t st) {
@@ -575,9 +579,11 @@ void batch_free(swept_batch_s* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-  if (b->side) (void)hipStreamDestroy(b->side);
+  for (int cl = 0; cl < 3; ++cl) {
+    if (b->side[cl]) (void)hipStreamDestroy(b->side[cl]);
+    if (b->ev_join[cl]) (void)hipEventDestroy(b->ev_join[cl]);
+  }
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
   if (b->items) (void)hipFree(b->items);
   if (b->res_items) (void)hipFree(b->res_items);
   if (b->slots) (void)hipFree(b->slots);
