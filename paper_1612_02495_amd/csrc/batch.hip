@@ -126,11 +126,14 @@ __host__ __device__ constexpr int res_class(int64_t n) { return n > kResQ * 64 *
 template <int KIND, typename T, int NW>
 __global__ void __launch_bounds__(64 * NW)
 resident_kernel(const BatchItem<T>* __restrict__ items, T* u, int64_t steps) {
-  constexpr int S = Radius<KIND>::value;
+  static_assert(Radius<KIND>::value <= 2, "one exchange holds two halo points per side");
   constexpr int Q = kResQ;
-  __shared__ T edF[2][NW][S];  // per wave: the first S points of its lane 0
-  __shared__ T edL[2][NW][S];  // per wave: the last S points of its lane 63
-  __shared__ T edC[2][S];      // the last S points of the ring (lane c-1)
+  // halo depth of one exchange: two points per side, which is one KS
+  // sub-step or two heat steps
+  constexpr int D = 2;
+  __shared__ T edF[2][NW][D];  // per wave: the first D points of its lane 0
+  __shared__ T edL[2][NW][D];  // per wave: the last D points of its lane 63
+  __shared__ T edC[2][D];      // the last D points of the ring (lane c-1)
   const BatchItem<T> pr = items[blockIdx.x];
   const int g = threadIdx.x;
   const int lane = g & 63;
@@ -146,70 +149,81 @@ resident_kernel(const BatchItem<T>* __restrict__ items, T* u, int64_t steps) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) A[i] = active ? ring[(int64_t)g * Q + i] : T(0);
   int sub = 0;
-  // Publish this lane's edge points, then gather the halos of src.
-  auto exchange = [&](const T (&src)[Q], T (&lo)[S], T (&hi)[S]) {
+  // Publish this lane's edge points, then gather the D halo points per side
+  // of src: lo[i] = point i - D, hi[i] = point Q + i.
+  auto exchange = [&](const T (&src)[Q], T (&lo)[D], T (&hi)[D]) {
     const int bf = sub & 1;
     if (busy) {
       if (active && lane == 0)
 #pragma unroll
-        for (int i = 0; i < S; ++i) edF[bf][wv][i] = src[i];
+        for (int i = 0; i < D; ++i) edF[bf][wv][i] = src[i];
       if (active && lane == 63)
 #pragma unroll
-        for (int i = 0; i < S; ++i) edL[bf][wv][i] = src[Q - S + i];
+        for (int i = 0; i < D; ++i) edL[bf][wv][i] = src[Q - D + i];
       if (g == c - 1)
 #pragma unroll
-        for (int i = 0; i < S; ++i) edC[bf][i] = src[Q - S + i];
+        for (int i = 0; i < D; ++i) edC[bf][i] = src[Q - D + i];
     }
     __syncthreads();
-    T xl[S] = {}, xr[S] = {};
+    T xl[D] = {}, xr[D] = {};
     if (first) {
 #pragma unroll
-      for (int i = 0; i < S; ++i) xl[i] = g == 0 ? edC[bf][i] : edL[bf][wv - 1][i];
+      for (int i = 0; i < D; ++i) xl[i] = g == 0 ? edC[bf][i] : edL[bf][wv - 1][i];
     }
     if (last) {
 #pragma unroll
-      for (int i = 0; i < S; ++i) xr[i] = g == c - 1 ? edF[bf][0][i] : edF[bf][wv + 1][i];
+      for (int i = 0; i < D; ++i) xr[i] = g == c - 1 ? edF[bf][0][i] : edF[bf][wv + 1][i];
     }
-    wave::halos<T, Q, S, true>(src, xl, xr, first, last, lo, hi);
+    wave::halos<T, Q, D, true>(src, xl, xr, first, last, lo, hi);
     ++sub;
   };
   const Consts<T> k = pr.k;
   if constexpr (KIND == kHeat) {
-    // two steps per iteration, A -> B -> A, so no register moves back
-    auto step = [&](const T (&src)[Q], T (&dst)[Q]) {
-      T lo[S], hi[S];
-      exchange(src, lo, hi);
+    // Two steps per exchange: the first step also forms points -1 and Q
+    // (the neighbours' edge points, from the same three values in the same
+    // order, so the same bits), the second uses them; A -> B -> A, so no
+    // register moves back.
+    for (int64_t s = 0; s + 1 < steps; s += 2) {
+      T lo[D], hi[D];
+      exchange(A, lo, hi);
       if (busy) {
+        const T m1 = heat_update(lo[0], lo[1], A[0], k);          // point -1
+        const T pq = heat_update(A[Q - 1], hi[0], hi[1], k);      // point Q
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-          dst[i] = heat_update(i > 0 ? src[i - 1] : lo[0], src[i], i + 1 < Q ? src[i + 1] : hi[0], k);
+          B[i] = heat_update(i > 0 ? A[i - 1] : lo[1], A[i], i + 1 < Q ? A[i + 1] : hi[0], k);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          A[i] = heat_update(i > 0 ? B[i - 1] : m1, B[i], i + 1 < Q ? B[i + 1] : pq, k);
       }
-    };
-    for (int64_t s = 0; s + 1 < steps; s += 2) {
-      step(A, B);
-      step(B, A);
     }
     if (steps & 1) {
-      step(A, B);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) A[i] = B[i];
-    }
-  } else {
-    for (int64_t s = 0; s < steps; ++s) {
-      T lo[S], hi[S];
+      T lo[D], hi[D];
       exchange(A, lo, hi);
       if (busy) {
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-          B[i] = ks_predictor(wave::at<T, Q, S>(A, lo, hi, i - 2), wave::at<T, Q, S>(A, lo, hi, i - 1), A[i],
-                              wave::at<T, Q, S>(A, lo, hi, i + 1), wave::at<T, Q, S>(A, lo, hi, i + 2), k);
+          B[i] = heat_update(i > 0 ? A[i - 1] : lo[1], A[i], i + 1 < Q ? A[i + 1] : hi[0], k);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) A[i] = B[i];
+      }
+    }
+  } else {
+    for (int64_t s = 0; s < steps; ++s) {
+      T lo[D], hi[D];
+      exchange(A, lo, hi);
+      if (busy) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          B[i] = ks_predictor(wave::at<T, Q, D>(A, lo, hi, i - 2), wave::at<T, Q, D>(A, lo, hi, i - 1), A[i],
+                              wave::at<T, Q, D>(A, lo, hi, i + 1), wave::at<T, Q, D>(A, lo, hi, i + 2), k);
       }
       exchange(B, lo, hi);
       if (busy) {
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-          A[i] = ks_final(A[i], wave::at<T, Q, S>(B, lo, hi, i - 2), wave::at<T, Q, S>(B, lo, hi, i - 1), B[i],
-                          wave::at<T, Q, S>(B, lo, hi, i + 1), wave::at<T, Q, S>(B, lo, hi, i + 2), k);
+          A[i] = ks_final(A[i], wave::at<T, Q, D>(B, lo, hi, i - 2), wave::at<T, Q, D>(B, lo, hi, i - 1), B[i],
+                          wave::at<T, Q, D>(B, lo, hi, i + 1), wave::at<T, Q, D>(B, lo, hi, i + 2), k);
       }
     }
   }
