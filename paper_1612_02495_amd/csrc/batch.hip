@@ -1,5 +1,9 @@
-// Batched swept runs: thousands of independent periodic grids of uneven size
-// advanced by one persistent kernel, launched as a captured HIP graph.
+// Batched swept runs: thousands of independent periodic grids of uneven size,
+// launched as one captured HIP graph.  The grids above the register-resident
+// limit (all of them with the COMPACT or WAVE engine) are advanced by one
+// persistent kernel of swept tiles; the smaller ones, with the default
+// engine, run whole in register-resident kernels (resident_kernel below) on
+// parallel branches of the same graph.
 //
 // Scheduling.  The grid of the persistent kernel is what the device holds
 // resident (occupancy x CUs).  Each workgroup takes the next problem from a
