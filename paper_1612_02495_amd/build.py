@@ -35,7 +35,7 @@ FLAGS = [
 ]
 
 SOURCES = ["plan.hip", "naive.hip", "phase_lds.hip", "phase_wave.hip", "phase_compact.hip", "autotune.hip", "batch.hip", "adjoint.hip",
-           "adjoint_ks.hip"]
+           "adjoint_ks.hip", "poison.hip"]
 
 
 def _compile(src: str) -> str:

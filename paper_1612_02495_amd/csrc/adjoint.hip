@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "poison.h"
 #include "swept.h"
 #include "wave_tile.h"
 
@@ -325,6 +326,7 @@ struct swept_adjoint_s {
   double dt = 0, dx = 0;
   int device = 0;
   bool have_forward = false;
+  bool poison = false;        // SWEPT_DEBUG_POISON: NaN-fill checkpoints and lambda slots before use
   double* consts = nullptr;   // Consts<double>[batch]
   double* ckpt = nullptr;     // K phases x batch x 2nt x 66
   double* lam_slots = nullptr;
@@ -380,6 +382,7 @@ int swept_adjoint_create(swept_adjoint* out, int32_t batch, int64_t n, int dtype
   a->nblk = (n + swept::adj::kRemThreads - 1) / swept::adj::kRemThreads;
   a->r = (int)(steps % swept::adj::kH);
   a->K = (int)(steps / swept::adj::kH);
+  a->poison = swept::debug_poison_requested();
   hipError_t e = hipGetDevice(&a->device);
   if (e != hipSuccess) {
     delete a;
@@ -422,6 +425,7 @@ int swept_forward_ckpt(swept_adjoint a, const void* u0, const double* alpha, voi
   hipLaunchKernelGGL(swept::adj::consts_kernel, dim3((unsigned)((a->batch + 63) / 64)), dim3(64), 0, st, alpha,
                      a->batch, a->dt, a->dx, k);
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess && a->poison) e = swept::poison_fill(a->ckpt, a->ckpt_bytes, 8, st);
   // leading classic steps: u_0 .. u_r kept for the reverse sweep
   if (e == hipSuccess) e = hipMemcpyAsync(a->rem, u0, state, hipMemcpyDeviceToDevice, st);
   for (int m = 0; m < a->r && e == hipSuccess; ++m) {
@@ -460,6 +464,8 @@ int swept_adjoint_run(swept_adjoint a, const void* g_uT, void* g_u0, double* g_a
   const size_t pslots = (size_t)a->batch * 2 * (size_t)a->nt * kSL;
   hipError_t e = zero(a->tiles, (int64_t)a->batch * a->nt, st);
   if (e == hipSuccess) e = zero(a->rparts, (int64_t)a->batch * a->nblk, st);
+  if (e == hipSuccess && a->poison)
+    e = swept::poison_fill(a->lam_slots, (size_t)a->batch * 2 * (size_t)a->nt * kSL * sizeof(double), 8, st);
   // lambda at tier r: from the swept sweep (or g_uT itself when T < 32)
   double* lam_r = a->r > 0 ? a->lam_a : static_cast<double*>(g_u0);
   if (a->K == 0) {

@@ -39,6 +39,7 @@
 #include <string>
 
 #include "internal.h"
+#include "poison.h"
 #include "swept.h"
 #include "wave_tile.h"
 
@@ -319,6 +320,7 @@ struct swept_ks_adjoint_s {
   swept::Consts<double> k{};
   swept::ksadj::JtCoef c{};
   bool have_forward = false;
+  bool poison = false;          // SWEPT_DEBUG_POISON: NaN-fill checkpoints and adjoint slots before use
   double* ckpt = nullptr;       // K phases x batch x 2nt x 68
   double* lam_slots = nullptr;  // batch x 2nt x 68
   double* rem = nullptr;        // (r+1) states x batch x n: u_0 .. u_r
@@ -373,6 +375,7 @@ int swept_ks_adjoint_create(swept_ks_adjoint* out, int32_t batch, int64_t n, int
   constexpr int spp = swept::ksadj::kH / 2;
   a->r = (int)(steps % spp);
   a->K = (int)(steps / spp);
+  a->poison = swept::debug_poison_requested();
   // same formulas as swept_plan_create for SWEPT_KS_RK2 (Sec. 4.1, Sec. 5)
   a->k.i4dx = 1.0 / (4.0 * dx);
   a->k.idx2 = 1.0 / (dx * dx);
@@ -414,8 +417,9 @@ int swept_ks_forward_ckpt(swept_ks_adjoint a, const void* u0, void* uT, void* st
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t total = (int64_t)a->batch * a->n;
   const size_t state = (size_t)total * sizeof(double);
+  hipError_t e = a->poison ? swept::poison_fill(a->ckpt, a->ckpt_bytes, 8, st) : hipSuccess;
   // leading classic steps: u_0 .. u_r kept for the reverse sweep
-  hipError_t e = hipMemcpyAsync(a->rem, u0, state, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(a->rem, u0, state, hipMemcpyDeviceToDevice, st);
   for (int m = 0; m < a->r && e == hipSuccess; ++m) {
     const double* um = a->rem + (size_t)m * total;
     hipLaunchKernelGGL(swept::ksadj::rem_pred_kernel, grid_for(total), dim3(kThreads), 0, st, um, a->tmp, a->k,
@@ -455,7 +459,7 @@ int swept_ks_adjoint_run(swept_ks_adjoint a, const void* g_uT, void* g_u0, void*
   const int64_t total = (int64_t)a->batch * a->n;
   const size_t state = (size_t)total * sizeof(double);
   const size_t pslots = (size_t)a->batch * 2 * (size_t)a->nt * kSL;
-  hipError_t e = hipSuccess;
+  hipError_t e = a->poison ? swept::poison_fill(a->lam_slots, pslots * sizeof(double), 8, st) : hipSuccess;
   // adjoint at step r: from the swept sweep (or g_uT itself when T < 8)
   double* lam_r = a->r > 0 ? a->lam_a : static_cast<double*>(g_u0);
   if (a->K == 0) {

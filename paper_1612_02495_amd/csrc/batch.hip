@@ -30,6 +30,7 @@
 
 #include "compact_tile.h"
 #include "internal.h"
+#include "poison.h"
 #include "swept.h"
 #include "wave_tile.h"
 
@@ -268,7 +269,8 @@ struct swept_batch_s {
   size_t slots_bytes = 0;
   int* queue = nullptr;
   int device = 0;
-  int engine = SWEPT_ENGINE_AUTO;  // AUTO runs the compacted engine
+  int engine = SWEPT_ENGINE_AUTO;
+  bool poison = false;             // SWEPT_DEBUG_POISON: NaN-fill the slots before each run
   int grid = 0;
   hipStream_t cap_stream = nullptr;
   hipStream_t side[3] = {};        // one branch per resident size class, beside the persistent kernel
@@ -408,6 +410,11 @@ hipError_t enqueue_batch(swept_batch_s* b, void* u, hipStream_t st) {
 
 hipError_t launch_swept(swept_batch_s* b, void* u, hipStream_t st) {
   if (b->nswept == 0) return hipSuccess;
+  if (b->poison) {
+    const hipError_t pe =
+        swept::poison_fill(b->slots, b->slots_bytes, b->dtype == SWEPT_F64 ? 8 : 4, st);
+    if (pe != hipSuccess) return pe;
+  }
   hipLaunchKernelGGL(swept::batch_reset_kernel, dim3(1), dim3(1), 0, st, b->queue);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -647,6 +654,7 @@ int swept_batch_create(swept_batch* out, int32_t nprob, const int64_t* n, int ki
     off += n[i];
   }
   b->total_points = off;
+  b->poison = swept::debug_poison_requested();
   // queue order: largest first (ties by input index)
   b->order.resize((size_t)nprob);
   std::iota(b->order.begin(), b->order.end(), 0);

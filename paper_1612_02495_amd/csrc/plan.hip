@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "poison.h"
 #include "swept.h"
 
 using swept::Consts;
@@ -120,6 +121,7 @@ struct swept_plan_s {
   size_t slots_bytes = 0;
   void* buf = nullptr;  // naive ping-pong / predictor buffer
   size_t buf_bytes = 0;
+  bool poison = false;  // SWEPT_DEBUG_POISON: NaN-fill the slots before each run
   Consts<double> kd{};
   Consts<float> kf{};
 };
@@ -331,6 +333,7 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
   }
   const size_t es = elem_size(dtype);
   p->slots_bytes = (size_t)(2 * p->nt) * (size_t)swept::slot_values(w, p->s) * es;
+  p->poison = swept::debug_poison_requested();
   p->buf_bytes = (size_t)n * es;
   e = hipMalloc(&p->slots, p->slots_bytes);
   if (e != hipSuccess) {
@@ -393,6 +396,10 @@ int swept_run(swept_plan p, void* u, int64_t steps, void* stream) {
   DeviceGuard g(p->device);
   if (!g.ok) return hip_fail(g.err, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->poison) {
+    const hipError_t pe = swept::poison_fill(p->slots, p->slots_bytes, (int)elem_size(p->dtype), st);
+    if (pe != hipSuccess) return hip_fail(pe, "workspace poison fill");
+  }
   const int64_t nphase = (int64_t)e.size() + 1;
   for (int64_t i = 0; i < nphase; ++i) {
     PhaseArgs a;
