@@ -15,6 +15,13 @@
  * every entry point below returns exactly what the plain timestepper returns
  * for the same precision and operation order.
  *
+ * Checking aid: with SWEPT_DEBUG_POISON set (to anything but "" or "0")
+ * when a plan, batch or adjoint plan is created, its edge slots (and the
+ * adjoints' checkpoints and lambda slots) are filled with quiet NaNs before
+ * each run, so an entry read before a phase wrote it shows up as NaN in the
+ * result.  Results are unchanged otherwise; the fill costs one pass over the
+ * workspace per run.
+ *
  * Schemes (Sec. 4.1 and Appendix; periodic boundaries, index (i+k) mod n,
  * except for the insulated rod):
  *   SWEPT_HEAT_FTCS  T_i^{m+1} = Fo (T_{i+1}^m + T_{i-1}^m) + (1 - 2 Fo) T_i^m,
