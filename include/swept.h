@@ -245,7 +245,7 @@ typedef struct swept_batch_s* swept_batch;
  * The grids live back to back in one device array in input order (offsets
  * from swept_batch_info).  With the default engine (AUTO, the same as
  * RESIDENT), every grid of at most 16384 points runs whole in one workgroup
- * of 1, 4 or 16 waves, 16 points per lane held in registers for all the
+ * of 1, 4, 8 or 16 waves, 16 points per lane held in registers for all the
  * steps, halos passed between lanes and waves each sub-step: a single tile
  * whose phase is the whole run, with no edge band through HBM; these
  * workgroups run beside the persistent kernel.  Every other grid (every grid

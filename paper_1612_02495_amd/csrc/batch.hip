@@ -112,7 +112,7 @@ batch_kernel(const BatchItem<T>* __restrict__ items, int nitems, T* u, T* slots,
 // Whole-grid kernel for the grids that fit one workgroup's registers
 // (n <= kResMax): one workgroup per grid, lane g of its NW waves holding
 // points [16 g, 16 g + 16) of the ring for all the steps.  Grids come in
-// three classes by size, each with its own workgroup size (1, 4 or 16
+// four classes by size, each with its own workgroup size (1, 4, 8 or 16
 // waves), so a small grid does not hold a whole CU's registers.  A grid this small
 // needs no decomposition in time: every sub-step updates every point, so no
 // lane idles on a triangle and no edge band is selected or stored; only the
@@ -122,11 +122,18 @@ batch_kernel(const BatchItem<T>* __restrict__ items, int nitems, T* u, T* slots,
 // same update in the same order as in every other engine, so the results are
 // the naive run's bit for bit.
 constexpr int kResQ = 16;                // points per lane
-constexpr int kResWaves[3] = {16, 4, 1};  // waves per workgroup of each size class
+constexpr int kResClasses = 4;
+constexpr int kResWaves[kResClasses] = {16, 8, 4, 1};  // waves per workgroup of each size class
 constexpr int kResMax = kResQ * 64 * 16;  // 16384 points
 
 // Size class of a resident grid: the smallest workgroup that holds it.
-__host__ __device__ constexpr int res_class(int64_t n) { return n > kResQ * 64 * 4 ? 0 : (n > kResQ * 64 ? 1 : 2); }
+__host__ __device__ constexpr int res_class(int64_t n) {
+  return n > kResQ * 64 * 8 ? 0 : (n > kResQ * 64 * 4 ? 1 : (n > kResQ * 64 ? 2 : 3));
+}
+// Side stream of each size class: the two small classes share one, so the
+// persistent kernel's stream and the side streams fit four hardware queues.
+constexpr int kResStreams = 3;
+constexpr int kResStreamOf[kResClasses] = {0, 1, 2, 2};
 
 template <int KIND, typename T, int NW>
 __global__ void __launch_bounds__(64 * NW)
@@ -262,7 +269,7 @@ struct swept_batch_s {
   int P = 16;                  // points per lane of the current tiling
   int32_t nswept = 0;          // grids run by the persistent swept kernel
   int32_t nres = 0;            // grids run whole by the resident kernels (AUTO engine)
-  int32_t res_count[3] = {};   // resident grids per size class (16, 4, 1 waves)
+  int32_t res_count[swept::kResClasses] = {};  // resident grids per size class (16, 8, 4, 1 waves)
   void* items = nullptr;       // device BatchItem<T>[nswept], queue order
   void* res_items = nullptr;   // device BatchItem<T>[nres], largest first (so by class)
   void* slots = nullptr;
@@ -273,9 +280,9 @@ struct swept_batch_s {
   bool poison = false;             // SWEPT_DEBUG_POISON: NaN-fill the slots before each run
   int grid = 0;
   hipStream_t cap_stream = nullptr;
-  hipStream_t side[3] = {};        // one branch per resident size class, beside the persistent kernel
+  hipStream_t side[swept::kResStreams] = {};  // branches of the resident classes, beside the persistent kernel
   hipEvent_t ev_fork = nullptr;
-  hipEvent_t ev_join[3] = {};
+  hipEvent_t ev_join[swept::kResStreams] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   void* graph_u = nullptr;
@@ -322,7 +329,7 @@ void launch_batch(const swept_batch_s* b, void* u, int64_t tiers, hipStream_t st
                      static_cast<T*>(u), static_cast<T*>(b->slots), tiers, b->queue);
 }
 
-// Launch the resident grids of size class cl (0: 16 waves, 1: 4, 2: 1).
+// Launch the resident grids of size class cl (0: 16 waves, 1: 8, 2: 4, 3: 1).
 template <int KIND, typename T>
 void launch_resident(const swept_batch_s* b, int cl, void* u, hipStream_t st) {
   const auto* items = static_cast<const BatchItem<T>*>(b->res_items);
@@ -337,8 +344,11 @@ void launch_resident(const swept_batch_s* b, int cl, void* u, hipStream_t st) {
   else if (cl == 1)
     hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[1]>), grid, block, 0, st, items + first,
                        static_cast<T*>(u), b->steps);
-  else
+  else if (cl == 2)
     hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[2]>), grid, block, 0, st, items + first,
+                       static_cast<T*>(u), b->steps);
+  else
+    hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[3]>), grid, block, 0, st, items + first,
                        static_cast<T*>(u), b->steps);
 }
 
@@ -376,34 +386,37 @@ hipError_t launch_resident_class(swept_batch_s* b, int cl, void* u, hipStream_t 
 hipError_t ensure_side(swept_batch_s* b) {
   hipError_t e = hipSuccess;
   if (!b->ev_fork) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
-  for (int cl = 0; cl < 3 && e == hipSuccess; ++cl) {
-    if (!b->side[cl]) e = hipStreamCreateWithFlags(&b->side[cl], hipStreamNonBlocking);
-    if (e == hipSuccess && !b->ev_join[cl]) e = hipEventCreateWithFlags(&b->ev_join[cl], hipEventDisableTiming);
+  for (int q = 0; q < swept::kResStreams && e == hipSuccess; ++q) {
+    if (!b->side[q]) e = hipStreamCreateWithFlags(&b->side[q], hipStreamNonBlocking);
+    if (e == hipSuccess && !b->ev_join[q]) e = hipEventCreateWithFlags(&b->ev_join[q], hipEventDisableTiming);
   }
   return e;
 }
 
 hipError_t launch_swept(swept_batch_s* b, void* u, hipStream_t st);
 
-// The grids are independent, so the kernels run side by side: each resident
-// size class goes on a side stream of its own, forked from and joined back
-// to `st` by events (parallel branches of the captured graph), beside the
-// persistent kernel on `st`.  Run one after another, the classes would end
-// well after the persistent kernel (heat: 65.7 ms against 52.0 ms).
+// The grids are independent, so the kernels run side by side: the resident
+// size classes go on side streams (the two small ones sharing one), forked
+// from and joined back to `st` by events (parallel branches of the captured
+// graph), beside the persistent kernel on `st`.  Run one after another, the
+// classes would end well after the persistent kernel (heat: 65.7 ms against
+// 52.0 ms).
 hipError_t enqueue_batch(swept_batch_s* b, void* u, hipStream_t st) {
   if (b->nres == 0) return launch_swept(b, u, st);
+  bool used[swept::kResStreams] = {};
+  for (int cl = 0; cl < swept::kResClasses; ++cl)
+    if (b->res_count[cl] > 0) used[swept::kResStreamOf[cl]] = true;
   hipError_t e = ensure_side(b);
   if (e == hipSuccess) e = hipEventRecord(b->ev_fork, st);
-  for (int cl = 0; cl < 3 && e == hipSuccess; ++cl) {
-    if (b->res_count[cl] == 0) continue;
-    e = hipStreamWaitEvent(b->side[cl], b->ev_fork, 0);
-    if (e == hipSuccess) e = launch_resident_class(b, cl, u, b->side[cl]);
-  }
+  for (int q = 0; q < swept::kResStreams && e == hipSuccess; ++q)
+    if (used[q]) e = hipStreamWaitEvent(b->side[q], b->ev_fork, 0);
+  for (int cl = 0; cl < swept::kResClasses && e == hipSuccess; ++cl)
+    if (b->res_count[cl] > 0) e = launch_resident_class(b, cl, u, b->side[swept::kResStreamOf[cl]]);
   if (e == hipSuccess) e = launch_swept(b, u, st);
-  for (int cl = 0; cl < 3 && e == hipSuccess; ++cl) {
-    if (b->res_count[cl] == 0) continue;
-    e = hipEventRecord(b->ev_join[cl], b->side[cl]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join[cl], 0);
+  for (int q = 0; q < swept::kResStreams && e == hipSuccess; ++q) {
+    if (!used[q]) continue;
+    e = hipEventRecord(b->ev_join[q], b->side[q]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join[q], 0);
   }
   return e;
 }
@@ -593,7 +606,7 @@ int build_tiling(swept_batch_s* b, int engine, int P) {
   b->slots_bytes = slot_values * es;
   b->nswept = (int32_t)nsw;
   b->nres = (int32_t)nre;
-  for (int cl = 0; cl < 3; ++cl) b->res_count[cl] = 0;
+  for (int cl = 0; cl < swept::kResClasses; ++cl) b->res_count[cl] = 0;
   for (int32_t i : b->order)
     if (resident(b, engine, i)) ++b->res_count[swept::res_class(b->n[(size_t)i])];
   b->P = P;
@@ -604,9 +617,9 @@ void batch_free(swept_batch_s* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-  for (int cl = 0; cl < 3; ++cl) {
-    if (b->side[cl]) (void)hipStreamDestroy(b->side[cl]);
-    if (b->ev_join[cl]) (void)hipEventDestroy(b->ev_join[cl]);
+  for (int q = 0; q < swept::kResStreams; ++q) {
+    if (b->side[q]) (void)hipStreamDestroy(b->side[q]);
+    if (b->ev_join[q]) (void)hipEventDestroy(b->ev_join[q]);
   }
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   if (b->items) (void)hipFree(b->items);

@@ -16,10 +16,11 @@ pytestmark = pytest.mark.gpu
 def _sizes(seed, m):
     rng = np.random.default_rng(seed)
     # uneven halves, one-tile rings, multi-tile rings, the 2^16 maximum; for
-    # the whole-grid kernel: 2 and 3 lanes, exactly one wave (1024), one lane
-    # into a second wave (1040), all 16 waves (16384) and the first size
-    # beyond it (16400, swept)
-    base = [32, 48, 256, 272, 1008, 1024, 1040, 2064, 4096, 5008, 16384, 16400, 65536]
+    # the whole-grid kernels: 2 and 3 lanes, exactly one wave (1024), one lane
+    # into a second wave (1040), the edges of the 4-, 8- and 16-wave classes
+    # (4096 / 4112, 8192 / 8208, 16384) and the first size beyond them
+    # (16400, swept)
+    base = [32, 48, 256, 272, 1008, 1024, 1040, 2064, 4096, 4112, 5008, 8192, 8208, 16384, 16400, 65536]
     extra = list(16 * rng.integers(2, 700, size=m - len(base)))
     return np.array(base + extra, dtype=np.int64)
 
