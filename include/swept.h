@@ -113,8 +113,14 @@ typedef struct swept_plan_s* swept_plan;
  * Discretisation constants are formed once on the host in double and, for
  * SWEPT_F32, rounded once to float: Fo = (alpha*dt)/(dx*dx), 1-2Fo,
  * 1/(4dx), 1/dx^2, (1/dx^2)^2, dt, dt/2 (inverses instead of divisions,
- * Sec. 5).  Errors: EINVAL (bad argument), EUNSUPPORTED (n not tileable with
- * a supported width), ENOMEM / EDEVICE (allocation).
+ * Sec. 5).  Size limit: a phase launches one workgroup per tile and a
+ * dispatch counts at most 2^32 - 1 work-items, so n / tile_width tiles times
+ * the engine's work-items per tile (64 for the register engines, up to 256
+ * for LDS) must stay below 2^32 -- e.g. n < 2^36 at tile width 1024; the
+ * plan fails with EUNSUPPORTED otherwise (naive_run takes any n).  Indices
+ * are 64-bit throughout.  Errors: EINVAL (bad argument), EUNSUPPORTED (n not
+ * tileable with a supported width, or too many tiles), ENOMEM / EDEVICE
+ * (allocation).
  */
 int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt, double dx,
                       double alpha, int tile_width, int steps_per_cycle);
@@ -148,7 +154,8 @@ int swept_plan_info(swept_plan p, int* tile_width, int* steps_per_cycle, size_t*
  * requires P in {8, 16} for either kind; otherwise the call fails with
  * EUNSUPPORTED and the plan keeps its engine.  Every engine computes the
  * same values bit for bit and leaves the same edge slots, so the choice
- * changes only the speed.
+ * changes only the speed.  An engine whose launch would exceed the size limit
+ * of swept_plan_create also fails with EUNSUPPORTED.
  */
 int swept_plan_set_engine(swept_plan p, int engine);
 
@@ -257,7 +264,9 @@ typedef struct swept_batch_s* swept_batch;
  * tilings, edge bands through HBM (Sec. 4.2-4.3), by one persistent kernel:
  * each workgroup pulls the next grid, largest first, from a device counter
  * and advances it through all of its phases.  The plan owns the edge slots,
- * the grid descriptors and the counter.  Errors: EINVAL, EUNSUPPORTED,
+ * the grid descriptors and the counter.  Each resident size class is one
+ * launch of one workgroup per grid, so more than 2^32 / (64 x its waves)
+ * grids of one class fail with EUNSUPPORTED.  Errors: EINVAL, EUNSUPPORTED,
  * ENOMEM, EDEVICE.
  */
 int swept_batch_create(swept_batch* out, int32_t nprob, const int64_t* n, int kind, int dtype, const double* dt,
@@ -317,7 +326,9 @@ typedef struct swept_adjoint_s* swept_adjoint;
  * scheme and keep their grids.  Workspace: about 2.06 n x 8 bytes per grid
  * per phase of checkpoints, (steps mod 32 + 1) grids per grid of classic
  * states, plus O(n) buffers -- all owned by the plan (swept_adjoint_info
- * reports the checkpoint size).  Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE.
+ * reports the checkpoint size).  batch x n (n rounded up to 256) must stay
+ * below 2^32, the work-items of one classic-step launch; larger requests
+ * fail with EUNSUPPORTED.  Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE.
  */
 int swept_adjoint_create(swept_adjoint* out, int32_t batch, int64_t n, int dtype, double dt, double dx,
                          int64_t steps);
@@ -375,6 +386,8 @@ typedef struct swept_ks_adjoint_s* swept_ks_adjoint;
  * Workspace: about 2.1 n x 8 bytes per grid per phase of checkpoints,
  * (steps mod 8 + 1) grids per grid of classic states, plus O(n) buffers --
  * all owned by the plan (swept_ks_adjoint_info reports the checkpoint size).
+ * batch x n (rounded up to 256) must stay below 2^32, the work-items of one
+ * classic-step launch; larger requests fail with EUNSUPPORTED.
  * Errors: EINVAL, EUNSUPPORTED, ENOMEM.
  */
 int swept_ks_adjoint_create(swept_ks_adjoint* out, int32_t batch, int64_t n, int dtype, double dt, double dx,

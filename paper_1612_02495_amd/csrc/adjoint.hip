@@ -28,6 +28,7 @@
 // blocks in a fixed order: the result does not depend on scheduling.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <string>
 #include <vector>
 
@@ -371,6 +372,10 @@ int swept_adjoint_create(swept_adjoint* out, int32_t batch, int64_t n, int dtype
   if (n < kW || n % kW != 0) return afail(SWEPT_EUNSUPPORTED, "n must be a positive multiple of 64");
   if (steps < 1) return afail(SWEPT_EINVAL, "steps must be >= 1");
   if (!std::isfinite(dt) || !std::isfinite(dx) || dx == 0.0) return afail(SWEPT_EINVAL, "dt, dx must be finite, dx != 0");
+  // the remainder steps launch one work-item per point of the batch
+  const int64_t nblk = (n + swept::adj::kRemThreads - 1) / swept::adj::kRemThreads;
+  if ((int64_t)batch * nblk * swept::adj::kRemThreads > (int64_t)UINT32_MAX)
+    return afail(SWEPT_EUNSUPPORTED, "batch x n exceeds one launch (2^32 - 1 work-items)");
   auto* a = new (std::nothrow) swept_adjoint_s();
   if (!a) return afail(SWEPT_ENOMEM, "host allocation failed");
   a->batch = batch;
@@ -379,7 +384,7 @@ int swept_adjoint_create(swept_adjoint* out, int32_t batch, int64_t n, int dtype
   a->dt = dt;
   a->dx = dx;
   a->nt = n / kW;
-  a->nblk = (n + swept::adj::kRemThreads - 1) / swept::adj::kRemThreads;
+  a->nblk = nblk;
   a->r = (int)(steps % swept::adj::kH);
   a->K = (int)(steps / swept::adj::kH);
   a->poison = swept::debug_poison_requested();

@@ -36,6 +36,7 @@
 // left p = x (x < a + 2), right p = x - a + 2 (x >= a - 2).
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <string>
 
 #include "internal.h"
@@ -364,8 +365,9 @@ int swept_ks_adjoint_create(swept_ks_adjoint* out, int32_t batch, int64_t n, int
   if (!std::isfinite(dt) || !std::isfinite(dx) || dx == 0.0)
     return kfail(SWEPT_EINVAL, "dt, dx must be finite, dx != 0");
   const int64_t total = (int64_t)batch * n;
-  if ((total + kThreads - 1) / kThreads > 0x7fffffff || n / kW > 0x7fffffff)
-    return kfail(SWEPT_EINVAL, "batch x n too large for one launch");
+  // the remainder steps launch one work-item per point of the batch
+  if ((total + kThreads - 1) / kThreads * kThreads > (int64_t)UINT32_MAX)
+    return kfail(SWEPT_EUNSUPPORTED, "batch x n exceeds one launch (2^32 - 1 work-items)");
   auto* a = new (std::nothrow) swept_ks_adjoint_s();
   if (!a) return kfail(SWEPT_ENOMEM, "host allocation failed");
   a->batch = batch;

@@ -24,6 +24,7 @@
 // LDS band buffers and staging rows of its own for every wave).
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -560,6 +561,13 @@ hipError_t upload(void** out, const void* host, size_t bytes) {
 // swept grids for an engine and P points per lane.  On failure the plan
 // keeps its previous tiling.
 int build_tiling(swept_batch_s* b, int engine, int P) {
+  int32_t count[swept::kResClasses] = {};
+  for (int32_t i : b->order)
+    if (resident(b, engine, i)) ++count[swept::res_class(b->n[(size_t)i])];
+  // one launch per class, one workgroup per grid: its work-items must fit 32 bits
+  for (int cl = 0; cl < swept::kResClasses; ++cl)
+    if ((int64_t)count[cl] * 64 * swept::kResWaves[cl] > (int64_t)UINT32_MAX)
+      return bfail(SWEPT_EUNSUPPORTED, "too many resident grids of one size class for one launch");
   size_t slot_values = 0, item_bytes = 0, res_bytes = 0;
   const void* host_items = nullptr;
   const void* host_res = nullptr;
@@ -606,9 +614,7 @@ int build_tiling(swept_batch_s* b, int engine, int P) {
   b->slots_bytes = slot_values * es;
   b->nswept = (int32_t)nsw;
   b->nres = (int32_t)nre;
-  for (int cl = 0; cl < swept::kResClasses; ++cl) b->res_count[cl] = 0;
-  for (int32_t i : b->order)
-    if (resident(b, engine, i)) ++b->res_count[swept::res_class(b->n[(size_t)i])];
+  for (int cl = 0; cl < swept::kResClasses; ++cl) b->res_count[cl] = count[cl];
   b->P = P;
   return SWEPT_OK;
 }

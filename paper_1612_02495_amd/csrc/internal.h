@@ -47,6 +47,8 @@ template <int KIND, typename T>
 hipError_t launch_phase_lds(const PhaseArgs& a, const Consts<T>& k, hipStream_t st);
 template <int KIND, typename T>
 size_t phase_lds_bytes(int w);
+// Work-items per tile of the LDS engine (the register engines use one wave64).
+int phase_lds_threads(int w);
 
 template <int KIND, typename T>
 hipError_t launch_phase_wave(const PhaseArgs& a, const Consts<T>& k, hipStream_t st);

@@ -14,12 +14,14 @@ __device__ __forceinline__ int64_t wrap_once(int64_t i, int64_t n) {
   return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
+__device__ __forceinline__ int64_t first_index() { return (int64_t)blockIdx.x * kNaiveThreads + threadIdx.x; }
+__device__ __forceinline__ int64_t stride() { return (int64_t)gridDim.x * kNaiveThreads; }
+
 template <typename T>
 __global__ void __launch_bounds__(kNaiveThreads)
 naive_heat_kernel(const T* __restrict__ in, T* __restrict__ out, int64_t n, Consts<T> k) {
-  const int64_t i = (int64_t)blockIdx.x * kNaiveThreads + threadIdx.x;
-  if (i >= n) return;
-  out[i] = heat_update(in[wrap_once(i - 1, n)], in[i], in[wrap_once(i + 1, n)], k);
+  for (int64_t i = first_index(); i < n; i += stride())
+    out[i] = heat_update(in[wrap_once(i - 1, n)], in[i], in[wrap_once(i + 1, n)], k);
 }
 
 // Insulated rod (Sec. 4.1): nodes 0 and n-1 take the mirror ghost about
@@ -27,32 +29,37 @@ naive_heat_kernel(const T* __restrict__ in, T* __restrict__ out, int64_t n, Cons
 template <typename T>
 __global__ void __launch_bounds__(kNaiveThreads)
 naive_heat_insulated_kernel(const T* __restrict__ in, T* __restrict__ out, int64_t n, Consts<T> k) {
-  const int64_t i = (int64_t)blockIdx.x * kNaiveThreads + threadIdx.x;
-  if (i >= n) return;
-  const T left = in[i == 0 ? 1 : i - 1];
-  const T right = in[i == n - 1 ? n - 2 : i + 1];
-  out[i] = heat_update(left, in[i], right, k);
+  for (int64_t i = first_index(); i < n; i += stride()) {
+    const T left = in[i == 0 ? 1 : i - 1];
+    const T right = in[i == n - 1 ? n - 2 : i + 1];
+    out[i] = heat_update(left, in[i], right, k);
+  }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kNaiveThreads)
 naive_ks_predictor_kernel(const T* __restrict__ u, T* __restrict__ q, int64_t n, Consts<T> k) {
-  const int64_t i = (int64_t)blockIdx.x * kNaiveThreads + threadIdx.x;
-  if (i >= n) return;
-  q[i] = ks_predictor(u[wrap_once(i - 2, n)], u[wrap_once(i - 1, n)], u[i], u[wrap_once(i + 1, n)],
-                      u[wrap_once(i + 2, n)], k);
+  for (int64_t i = first_index(); i < n; i += stride())
+    q[i] = ks_predictor(u[wrap_once(i - 2, n)], u[wrap_once(i - 1, n)], u[i], u[wrap_once(i + 1, n)],
+                        u[wrap_once(i + 2, n)], k);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kNaiveThreads)
 naive_ks_final_kernel(T* __restrict__ u, const T* __restrict__ q, int64_t n, Consts<T> k) {
-  const int64_t i = (int64_t)blockIdx.x * kNaiveThreads + threadIdx.x;
-  if (i >= n) return;
-  u[i] = ks_final(u[i], q[wrap_once(i - 2, n)], q[wrap_once(i - 1, n)], q[i], q[wrap_once(i + 1, n)],
-                  q[wrap_once(i + 2, n)], k);
+  for (int64_t i = first_index(); i < n; i += stride())
+    u[i] = ks_final(u[i], q[wrap_once(i - 2, n)], q[wrap_once(i - 1, n)], q[i], q[wrap_once(i + 1, n)],
+                    q[wrap_once(i + 2, n)], k);
 }
 
-inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kNaiveThreads - 1) / kNaiveThreads)); }
+// One thread per point up to kNaiveMaxBlocks blocks (2^30 points); larger
+// rings loop, so every grid size fits one launch.
+constexpr int64_t kNaiveMaxBlocks = int64_t(1) << 22;
+
+inline dim3 grid_for(int64_t n) {
+  const int64_t blocks = (n + kNaiveThreads - 1) / kNaiveThreads;
+  return dim3((unsigned)(blocks < kNaiveMaxBlocks ? blocks : kNaiveMaxBlocks));
+}
 
 }  // namespace
 

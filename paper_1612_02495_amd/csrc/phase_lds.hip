@@ -155,9 +155,11 @@ size_t phase_lds_bytes(int w) {
   return (size_t)(2 * (w + 2 * S) + 2 * slot_values(w, S)) * sizeof(T);
 }
 
+int phase_lds_threads(int w) { return w >= kLdsThreads ? kLdsThreads : ((w + 63) / 64) * 64; }
+
 template <int KIND, typename T>
 hipError_t launch_phase_lds(const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
-  const int threads = a.w >= kLdsThreads ? kLdsThreads : ((a.w + 63) / 64) * 64;
+  const int threads = phase_lds_threads(a.w);
   const size_t lds = phase_lds_bytes<KIND, T>(a.w);
   auto kern = a.hv == 0 ? phase_lds_kernel<KIND, T, 0>
               : (a.hl == 0 ? phase_lds_kernel<KIND, T, 2> : phase_lds_kernel<KIND, T, 1>);

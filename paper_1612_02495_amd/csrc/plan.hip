@@ -1,6 +1,7 @@
 // C ABI of the swept library: argument validation, tiling, phase schedule,
 // workspace ownership and launch sequencing (declared in include/swept.h).
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -142,12 +143,25 @@ bool engine_supports(int engine, int kind, int w) {
 
 // The engine that runs the phases: the chosen one, or for AUTO the compacted
 // engine where it has a kernel, else the register engine, else LDS.
-int resolved_engine(const swept_plan_s* p) {
-  if (p->engine != SWEPT_ENGINE_AUTO) return p->engine;
-  const int st = stencil_of(p->kind);
-  if (swept::compact_engine_supports(st, p->w)) return SWEPT_ENGINE_COMPACT;
-  return swept::wave_engine_supports(st, p->w) ? SWEPT_ENGINE_WAVE : SWEPT_ENGINE_LDS;
+int resolve_engine(int engine, int kind, int w) {
+  if (engine != SWEPT_ENGINE_AUTO) return engine;
+  const int st = stencil_of(kind);
+  if (swept::compact_engine_supports(st, w)) return SWEPT_ENGINE_COMPACT;
+  return swept::wave_engine_supports(st, w) ? SWEPT_ENGINE_WAVE : SWEPT_ENGINE_LDS;
 }
+
+int resolved_engine(const swept_plan_s* p) { return resolve_engine(p->engine, p->kind, p->w); }
+
+// A phase is one launch of one workgroup per tile, and a dispatch counts its
+// work-items in 32 bits: n / w tiles times the engine's work-items per tile
+// must stay below 2^32.
+bool launch_fits(int engine, int kind, int w, int64_t nt) {
+  const int e = resolve_engine(engine, kind, w);
+  const int64_t per_tile = e == SWEPT_ENGINE_LDS ? swept::phase_lds_threads(w) : 64;
+  return nt * per_tile <= (int64_t)UINT32_MAX;
+}
+
+const char* kTooManyTiles = "n / tile_width tiles exceed one launch of this engine (2^32 - 1 work-items)";
 
 template <int KIND, typename T>
 hipError_t launch_phase(const swept_plan_s* p, const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
@@ -331,6 +345,15 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
     delete p;
     return fail(SWEPT_EUNSUPPORTED, "tile too wide for the LDS of this device");
   }
+  p->engine = tuned_engine;
+  p->lds_fits = lds <= (size_t)max_lds;
+  // a tuned LDS choice that this device's LDS cannot hold falls back to AUTO
+  // (a register engine: the width check above guarantees one exists)
+  if (!p->lds_fits && p->engine == SWEPT_ENGINE_LDS) p->engine = SWEPT_ENGINE_AUTO;
+  if (!launch_fits(p->engine, kind, w, p->nt)) {
+    delete p;
+    return fail(SWEPT_EUNSUPPORTED, kTooManyTiles);
+  }
   const size_t es = elem_size(dtype);
   p->slots_bytes = (size_t)(2 * p->nt) * (size_t)swept::slot_values(w, p->s) * es;
   p->poison = swept::debug_poison_requested();
@@ -346,11 +369,6 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
     delete p;
     return fail(SWEPT_ENOMEM, std::string("hipMalloc(naive buffer): ") + hipGetErrorString(e));
   }
-  p->engine = tuned_engine;
-  p->lds_fits = lds <= (size_t)max_lds;
-  // a tuned LDS choice that this device's LDS cannot hold falls back to AUTO
-  // (a register engine: the width check above guarantees one exists)
-  if (!p->lds_fits && p->engine == SWEPT_ENGINE_LDS) p->engine = SWEPT_ENGINE_AUTO;
   *out = p;
   return SWEPT_OK;
 }
@@ -366,6 +384,7 @@ int swept_plan_set_engine(swept_plan p, int engine) {
                                                                      : "no kernel of this engine for this kind");
   if (engine == SWEPT_ENGINE_LDS && !p->lds_fits)
     return fail(SWEPT_EUNSUPPORTED, "tile too wide for the LDS of this device");
+  if (!launch_fits(engine, p->kind, p->w, p->nt)) return fail(SWEPT_EUNSUPPORTED, kTooManyTiles);
   p->engine = engine;
   return SWEPT_OK;
 }

@@ -13,6 +13,7 @@ from paper_1612_02495_amd import _lib
     ((2, 1024, 0, 1e-6, 1e-3, 100), _lib.SWEPT_EUNSUPPORTED),  # f32
     ((2, 1024, 1, 1e-6, 1e-3, 0), _lib.SWEPT_EINVAL),          # steps
     ((2, 1024, 1, 1e-6, 0.0, 10), _lib.SWEPT_EINVAL),          # dx
+    ((65535, 65600, 1, 1e-6, 1e-3, 10), _lib.SWEPT_EUNSUPPORTED),  # batch x n beyond one launch
 ])
 def test_adjoint_create_rejects(args, code):
     h = ctypes.c_void_p()
@@ -37,6 +38,7 @@ def test_adjoint_null_handles():
     ((1, 1024, 1, 0.005, 0.5, 0), _lib.SWEPT_EINVAL),          # steps
     ((1, 1024, 1, 0.005, 0.0, 10), _lib.SWEPT_EINVAL),         # dx
     ((1, 1024, 1, float("nan"), 0.5, 10), _lib.SWEPT_EINVAL),  # dt
+    ((65535, 65600, 1, 0.005, 0.5, 10), _lib.SWEPT_EUNSUPPORTED),  # batch x n beyond one launch
 ])
 def test_ks_adjoint_create_rejects(args, code):
     h = ctypes.c_void_p()
