@@ -32,6 +32,7 @@
 #include <string>
 #include <vector>
 
+#include "device_guard.h"
 #include "internal.h"
 #include "poison.h"
 #include "swept.h"
@@ -423,6 +424,8 @@ int swept_adjoint_create(swept_adjoint* out, int32_t batch, int64_t n, int dtype
 int swept_forward_ckpt(swept_adjoint a, const void* u0, const double* alpha, void* uT, void* stream) {
   if (!a) return afail(SWEPT_EINVAL, "adjoint plan must not be NULL");
   if (!u0 || !alpha || !uT) return afail(SWEPT_EINVAL, "u0, alpha and uT must not be NULL");
+  swept::DeviceGuard g(a->device);
+  if (!g.ok) return ahip(g.err, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t total = (int64_t)a->batch * a->n;
   const size_t state = (size_t)total * sizeof(double);
@@ -462,6 +465,8 @@ int swept_adjoint_run(swept_adjoint a, const void* g_uT, void* g_u0, double* g_a
   if (!a) return afail(SWEPT_EINVAL, "adjoint plan must not be NULL");
   if (!g_uT || !g_u0 || !g_alpha) return afail(SWEPT_EINVAL, "g_uT, g_u0 and g_alpha must not be NULL");
   if (!a->have_forward) return afail(SWEPT_EINVAL, "swept_forward_ckpt must run first");
+  swept::DeviceGuard g(a->device);
+  if (!g.ok) return ahip(g.err, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t total = (int64_t)a->batch * a->n;
   const size_t state = (size_t)total * sizeof(double);
@@ -517,6 +522,7 @@ int swept_adjoint_info(swept_adjoint a, size_t* checkpoint_bytes, int* tile_widt
 
 void swept_adjoint_destroy(swept_adjoint a) {
   if (!a) return;
+  swept::DeviceGuard g(a->device);
   adj_free(a);
 }
 

@@ -39,6 +39,7 @@
 #include <cstdint>
 #include <string>
 
+#include "device_guard.h"
 #include "internal.h"
 #include "poison.h"
 #include "swept.h"
@@ -320,6 +321,7 @@ struct swept_ks_adjoint_s {
   int r = 0;  // leading classic steps
   swept::Consts<double> k{};
   swept::ksadj::JtCoef c{};
+  int device = 0;  // current device at create: owns the buffers
   bool have_forward = false;
   bool poison = false;          // SWEPT_DEBUG_POISON: NaN-fill checkpoints and adjoint slots before use
   double* ckpt = nullptr;       // K phases x batch x 2nt x 68
@@ -388,6 +390,11 @@ int swept_ks_adjoint_create(swept_ks_adjoint* out, int32_t batch, int64_t n, int
   a->c.c1 = a->k.idx2 - 4.0 * a->k.idx4;
   a->c.c0 = -(6.0 * a->k.idx4 - 2.0 * a->k.idx2);
   a->c.c2 = -a->k.idx4;
+  const hipError_t de = hipGetDevice(&a->device);
+  if (de != hipSuccess) {
+    delete a;
+    return khip(de, "hipGetDevice");
+  }
   const size_t state = (size_t)total * sizeof(double);
   const size_t slots = (size_t)batch * 2 * (size_t)a->nt * kSL * sizeof(double);
   a->ckpt_bytes = (size_t)a->K * slots;
@@ -416,6 +423,8 @@ int swept_ks_adjoint_create(swept_ks_adjoint* out, int32_t batch, int64_t n, int
 int swept_ks_forward_ckpt(swept_ks_adjoint a, const void* u0, void* uT, void* stream) {
   if (!a) return kfail(SWEPT_EINVAL, "KS adjoint plan must not be NULL");
   if (!u0 || !uT) return kfail(SWEPT_EINVAL, "u0 and uT must not be NULL");
+  swept::DeviceGuard g(a->device);
+  if (!g.ok) return khip(g.err, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t total = (int64_t)a->batch * a->n;
   const size_t state = (size_t)total * sizeof(double);
@@ -457,6 +466,8 @@ int swept_ks_adjoint_run(swept_ks_adjoint a, const void* g_uT, void* g_u0, void*
   if (!a) return kfail(SWEPT_EINVAL, "KS adjoint plan must not be NULL");
   if (!g_uT || !g_u0) return kfail(SWEPT_EINVAL, "g_uT and g_u0 must not be NULL");
   if (!a->have_forward) return kfail(SWEPT_EINVAL, "swept_ks_forward_ckpt must run first");
+  swept::DeviceGuard g(a->device);
+  if (!g.ok) return khip(g.err, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t total = (int64_t)a->batch * a->n;
   const size_t state = (size_t)total * sizeof(double);
@@ -508,6 +519,7 @@ int swept_ks_adjoint_info(swept_ks_adjoint a, size_t* checkpoint_bytes, int* til
 
 void swept_ks_adjoint_destroy(swept_ks_adjoint a) {
   if (!a) return;
+  swept::DeviceGuard g(a->device);
   ks_free(a);
 }
 

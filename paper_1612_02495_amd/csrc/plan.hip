@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "device_guard.h"
 #include "internal.h"
 #include "poison.h"
 #include "swept.h"
@@ -86,24 +87,6 @@ void make_schedule(int h, int64_t tiers, std::vector<int32_t>* e) {
   for (int64_t i = 0; i < full; ++i) e->push_back(h);
   if (rem) e->push_back((int32_t)rem);
 }
-
-struct DeviceGuard {
-  int prev = -1;
-  bool ok = true;
-  hipError_t err = hipSuccess;
-  explicit DeviceGuard(int dev) {
-    err = hipGetDevice(&prev);
-    if (err != hipSuccess) { ok = false; return; }
-    if (prev != dev) {
-      err = hipSetDevice(dev);
-      ok = err == hipSuccess;
-    }
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (ok && hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
-  }
-};
 
 }  // namespace
 
@@ -399,7 +382,7 @@ int swept_plan_info(swept_plan p, int* tile_width, int* steps_per_cycle, size_t*
 
 void swept_plan_destroy(swept_plan p) {
   if (!p) return;
-  DeviceGuard g(p->device);
+  swept::DeviceGuard g(p->device);
   if (p->slots) (void)hipFree(p->slots);
   if (p->buf) (void)hipFree(p->buf);
   delete p;
@@ -412,7 +395,7 @@ int swept_run(swept_plan p, void* u, int64_t steps, void* stream) {
   if (!u) return fail(SWEPT_EINVAL, "u must not be NULL");
   std::vector<int32_t> e;
   make_schedule(p->h, steps * tiers_per_step(p->kind), &e);
-  DeviceGuard g(p->device);
+  swept::DeviceGuard g(p->device);
   if (!g.ok) return hip_fail(g.err, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (p->poison) {
@@ -442,7 +425,7 @@ int naive_run(swept_plan p, void* u, int64_t steps, void* stream) {
   if (steps < 0) return fail(SWEPT_EINVAL, "steps must be >= 0");
   if (steps == 0) return SWEPT_OK;
   if (!u) return fail(SWEPT_EINVAL, "u must not be NULL");
-  DeviceGuard g(p->device);
+  swept::DeviceGuard g(p->device);
   if (!g.ok) return hip_fail(g.err, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t err = p->dtype == SWEPT_F64 ? run_naive<double>(p, static_cast<double*>(u), steps, p->kd, st)
