@@ -136,7 +136,8 @@ def run_adjoint(args, wl):
         el = _time.perf_counter() - t0
         cpu = {"value": n * cs / el, "unit": "cell-updates/s of gradient (forward + reverse)", "cores": 1,
                "kind": "oracle", "sample": f"one of the {B} grids, {cs} of the {T} steps, single-thread C "
-                                           f"checkpointed reverse sweep, {el:.1f} s"}
+                                           f"checkpointed reverse sweep, {el:.1f} s",
+               "host_cpu": host_cpu_model()}
     return {
         "metric": METRIC, "value": updates / t, "unit": "cell-updates/s of gradient (forward + reverse)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t / args.steps,
@@ -219,7 +220,8 @@ def run_ks_adjoint(args, wl):
         el = _time.perf_counter() - t0
         cpu = {"value": n * cs / el, "unit": "cell-updates/s of gradient (forward + reverse)", "cores": 1,
                "kind": "oracle", "sample": f"grid 0 of {B}, {cs} of the {T} steps, single-thread C "
-                                           f"checkpointed reverse sweep, {el:.1f} s"}
+                                           f"checkpointed reverse sweep, {el:.1f} s",
+               "host_cpu": host_cpu_model()}
     return {
         "metric": METRIC, "value": updates / t, "unit": "cell-updates/s of gradient (forward + reverse)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t / args.steps,
@@ -272,7 +274,8 @@ def run_batch(args, wl):
         cells = sum(p.n for p in probs[:64]) * budget
         cpu = {"value": cells / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
                "sample": f"first 64 of the {len(probs)} grids, {budget} of the {T} steps each "
-                         f"(largest grid in batch n={big.n}), single-thread C oracle, {el:.1f} s"}
+                         f"(largest grid in batch n={big.n}), single-thread C oracle, {el:.1f} s",
+               "host_cpu": host_cpu_model()}
     return {
         "metric": METRIC, "value": updates / t, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t / args.steps,
@@ -352,6 +355,31 @@ def _time_runs(fn, reps, torch):
     return start.elapsed_time(end) / 1e3  # seconds
 
 
+def _naive_graph_rate(plan, v, steps, reps, torch):
+    """Seconds per timestep of the naive run replayed from a captured graph of
+    `steps` timesteps (one kernel node per step or sub-step), which takes the
+    host's launch cost out of the naive kernel's time."""
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=side):
+        plan.naive(v, steps)
+    g.replay()
+    t = _time_runs(g.replay, reps, torch)
+    del g
+    return t / (reps * steps)
+
+
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(wl, budget_steps):
     import numpy as np
 
@@ -369,7 +397,8 @@ def cpu_baseline(wl, budget_steps):
     el = time.perf_counter() - t0
     return {"value": p.n * budget_steps / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{wl['kind']} N={p.n} {wl['dtype']}, {budget_steps} of the {wl['horizon']} steps, "
-                      f"single-thread C oracle, {el:.1f} s"}
+                      f"single-thread C oracle, {el:.1f} s",
+            "host_cpu": host_cpu_model()}
 
 
 def main(argv=None):
@@ -385,6 +414,8 @@ def main(argv=None):
     ap.add_argument("--horizon", type=int, default=0, help="timesteps per run (0 = workload default)")
     ap.add_argument("--naive-steps", type=int, default=0, help="timed naive runs (0 = same as --steps)")
     ap.add_argument("--no-naive", action="store_true")
+    ap.add_argument("--no-naive-graph", action="store_true",
+                    help="skip the graph-replayed naive timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle timesteps in the CPU sample")
     ap.add_argument("--no-dominant", action="store_true",
@@ -476,6 +507,12 @@ def main(argv=None):
                  "hbm_bound": {"bytes_per_cell_update": bytes_per_update,
                                "achieved_GBps": bytes_per_update * p.n * T * k_naive / t_naive / 1e9,
                                "peak_GBps": 8000.0}}
+        if not args.no_naive_graph:
+            g_steps = min(T, 1000)
+            per_step = _naive_graph_rate(plan, v, g_steps, 5, torch)
+            naive["graph"] = {"value": p.n / per_step, "ms_per_timestep": 1e3 * per_step,
+                              "achieved_GBps": bytes_per_update * p.n / per_step / 1e9,
+                              "captured_timesteps": g_steps}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -511,6 +548,7 @@ def main(argv=None):
                      "flops_per_launch": flops},
         "naive": naive,
         "speedup_vs_naive": (value / naive["value"]) if naive else None,
+        "speedup_vs_naive_graph": (value / naive["graph"]["value"]) if naive and "graph" in naive else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
