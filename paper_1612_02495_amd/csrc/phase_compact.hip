@@ -8,6 +8,17 @@
 namespace swept {
 namespace {
 
+// Tile of workgroup b when each XCD is given a contiguous run of tiles.  The
+// workgroups of one launch go to the 8 XCDs in turn (b mod 8), so this makes
+// the two tiles whose slots a phase reads sit, but for the runs' ends, on the
+// XCD that wrote them.  A bijection of [0, nt) for every nt.  Measured on the
+// N=2^20, w=1024 diamonds: heat FP64 +2.3%, FP32 +0.6%, KS -2.2% (so KS keeps
+// the plain order).
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nt) {
+  const int64_t q = nt / 8, r = nt % 8, x = b % 8;
+  return x * q + (x < r ? x : r) + b / 8;
+}
+
 // INS: heat on a rod with insulated ends.  The rod's nodes 0 and n-1 sit at
 // the ring seam: at the middle of the last tile of the shifted tiling
 // (parity 1), or at the first point of tile 0 and the last of tile nt-1
@@ -21,7 +32,7 @@ phase_compact_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, 
   constexpr int SLEN = W + 2 * S;
   __shared__ T sb[compact::Lds<KIND, P>::band];
   __shared__ T stg[compact::Lds<KIND, P>::stage];
-  const int64_t j = blockIdx.x;
+  const int64_t j = KIND == kHeat ? xcd_tile(blockIdx.x, nt) : (int64_t)blockIdx.x;
   const int64_t origin = j * (int64_t)W + (parity ? HALF : 0);
   T* sL = parity ? slots + (nt + j) * SLEN : slots + j * SLEN;
   T* sR = parity ? slots + ((j + 1) % nt) * SLEN : slots + (nt + j) * SLEN;
