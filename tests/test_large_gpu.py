@@ -5,14 +5,15 @@ beyond index 2^31 -- equal the oracle: after T steps a point depends only on
 the 2sT + 1 points around it, so the oracle run on that window as a periodic
 ring of exactly that length reproduces it (every point of the window enters
 its dependency cone once, through the same operations in the same order).
-Inputs are drawn on the device from a seeded generator.  A plan whose phase
-launch would exceed the 32-bit work-item count of one dispatch is refused
-before it allocates."""
+A batch with two grids of the maximum 2^30 points puts its other grids past
+element offset 2^31.  Inputs are drawn on the device from a seeded generator.
+A plan whose phase launch would exceed the 32-bit work-item count of one
+dispatch is refused before it allocates."""
 import numpy as np
 import pytest
 
 import oracle
-from paper_1612_02495_amd import Plan, SweptError
+from paper_1612_02495_amd import Batch, Plan, SweptError
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -74,3 +75,38 @@ def test_too_many_tiles_for_one_launch_is_refused():
     with pytest.raises(SweptError, match="exceed one launch"):
         Plan(2 ** 32, "heat", torch.float32, 1e-6, 1e-3, 1.0, tile_width=16)
     print("2^32 points at tile width 16 refused", flush=True)
+
+
+def test_batch_grids_beyond_2p31_offsets():
+    # two grids of the maximum 2^30 points (compacted swept tiles) put the two
+    # small grids behind them (register-resident) past element offset 2^31
+    sizes = np.array([2 ** 30, 2 ** 30, 4096, 48], dtype=np.int64)
+    steps = 3
+    print(f"batch f32 sizes={sizes.tolist()} steps={steps}", flush=True)
+    dx = 1.0 / sizes
+    dt = 0.3 * dx * dx
+    alpha = np.ones(sizes.size)
+    b = Batch(sizes, "heat", torch.float32, dt, dx, alpha, steps)
+    assert b.offsets[2] >= 2 ** 31  # beyond the int32 index range
+    g = torch.Generator(device="cuda")
+    g.manual_seed(30)
+    u0 = torch.rand(b.total_points, generator=g, device="cuda", dtype=torch.float32) * 2 - 1
+    u = u0.clone()
+    b.run(u)
+    torch.cuda.synchronize()
+    for i, (got, start) in enumerate(zip(b.split(u), b.split(u0))):
+        plan = Plan(int(sizes[i]), "heat", torch.float32, dt[i], dx[i], 1.0)  # naive only: any width
+        v = start.clone()
+        plan.naive(v, steps)
+        torch.cuda.synchronize()
+        assert torch.equal(got, v), f"grid {i} (n={sizes[i]})"
+        # the oracle on the periodic window around a few points of the grid
+        for x in (0, int(sizes[i]) // 2 + 3, int(sizes[i]) - 1):
+            w = _window(start, x, steps).astype(np.float32)
+            ref = oracle.heat(w, 1.0, dt[i], dx[i], steps, dtype=np.float32)
+            assert ref[steps] == got[x].item(), f"grid {i} point {x}"
+        plan.close()
+        del v
+    b.close()
+    del u, u0
+    torch.cuda.empty_cache()
