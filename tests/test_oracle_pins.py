@@ -96,6 +96,23 @@ def test_heat_binomial_exact_fo_quarter(steps):
     assert [Fraction(v) for v in got] == want
 
 
+@pytest.mark.parametrize("steps", [1, 2, 7, 9])
+def test_heat_binomial_exact_fo_quarter_f32(steps):
+    # The same binomial closed form in single precision: with integers in
+    # [-64, 64] every intermediate of up to 9 steps is k / 4^t with |k| <= 2^24,
+    # so FP32 arithmetic is exact too and the FP32 oracle must match bit for bit.
+    n = 16
+    u0 = inputs.dyadic_grid(n, seed=12)
+    dx = 2.0 ** -4
+    dt = dx * dx / 4.0
+    got = oracle.heat(u0, 1.0, dt, dx, steps, dtype=np.float32)
+    assert got.dtype == np.float32
+    ints = [int(v) for v in u0]
+    for i in range(n):
+        acc = sum(math.comb(2 * steps, j) * ints[(i - steps + j) % n] for j in range(2 * steps + 1))
+        assert Fraction(float(got[i])) == Fraction(acc, 4 ** steps), i
+
+
 def test_heat_conservation():
     n, steps, fo = 256, 500, 0.3
     rng = np.random.default_rng(5)
@@ -201,6 +218,16 @@ def test_ks_translation_bitwise_and_parity_symmetry():
     got = oracle.ks(mirrored, 0.005, 0.5, steps)
     want = -np.roll(base[::-1], 1)
     assert np.max(np.abs(got - want)) <= 1e-10 * max(1.0, np.max(np.abs(base)))
+
+
+def test_ks_f32_translation_bitwise():
+    # the FP32 path is as shift-invariant as the FP64 one: rolling the input
+    # rolls the output bit for bit (every point gets the same operations)
+    p = inputs.ks(n=200, steps=60)
+    base = oracle.ks(p.u0, p.dt, p.dx, p.steps, dtype=np.float32)
+    for s in (1, 3, 199):
+        got = oracle.ks(np.roll(p.u0, s), p.dt, p.dx, p.steps, dtype=np.float32)
+        assert np.array_equal(got, np.roll(base, s))
 
 
 def test_ks_f32_tracks_f64_short_horizon():
