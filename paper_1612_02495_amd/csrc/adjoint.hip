@@ -46,6 +46,7 @@ constexpr int kH = 32;  // w / 2: tiers of a full triangle
 constexpr int kA = 32;  // inner seam
 constexpr int kSL = kW + 2;
 constexpr int kRemThreads = 256;
+constexpr int kFwdPoints = 8;  // points per lane (and tiles per wave) of the checkpointing forward
 
 __global__ void consts_kernel(const double* __restrict__ alpha, int batch, double dt, double dx,
                               Consts<double>* __restrict__ k) {
@@ -68,24 +69,22 @@ __host__ __device__ constexpr uint64_t row_bits(int d) {
 // Lanes [lo, lo + 2): the two points of an edge band.
 __host__ __device__ constexpr uint64_t pair_bits(int lo) { return wave::range_bits(lo, lo + 2); }
 
-// Lane x inside [lo, lo + 2): the two points of an edge band.
-
 // One swept region of one tile, held in one wave64: lane x owns tile point x
 // and keeps the region's states u(x, d) in registers, tier by tier; the
 // neighbours of a point come from DPP lane shifts and the edge bands enter
 // and leave through per-lane registers, so there is no LDS and no barrier.
 //
-// MODE 0: forward phase writing checkpoint slots (or u_T).  MODE 1: fused
-// adjoint (recompute, lambda walk, dJ/dalpha terms).  HV: the region has a V
-// part (every phase but the first); HL: it has a Lambda part (every phase
-// but the last).  Slots are position-major [p][t & 1] as in the forward
-// engines: consumer left input p = x + 1, right input p = x - a; producer
-// left side p = x (x <= a), right side p = x - a + 1 (x >= a - 1).
-template <int MODE, bool HV, bool HL>
+// The fused reverse launch of one phase: recompute the region, walk lambda
+// down through it and add the dJ/dalpha terms.  HV: the region has a V part
+// (every phase but the first); HL: it has a Lambda part (every phase but the
+// last).  Slots are position-major [p][t & 1] as in the forward engines:
+// consumer left input p = x + 1, right input p = x - a; producer left side
+// p = x (x <= a), right side p = x - a + 1 (x >= a - 1).
+template <bool HV, bool HL>
 __global__ void __launch_bounds__(kW)
-region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const double* __restrict__ ck_in,
-              double* __restrict__ ck_out, const double* __restrict__ gT, double* lam_slots, double* __restrict__ g_ur,
-              double* __restrict__ partial, const Consts<double>* __restrict__ kb, int64_t n, int64_t nt, int p) {
+region_kernel(const double* __restrict__ ustart, const double* __restrict__ ck_in, const double* __restrict__ gT,
+              double* lam_slots, double* __restrict__ g_ur, double* __restrict__ partial,
+              const Consts<double>* __restrict__ kb, int64_t n, int64_t nt, int p) {
   using wave::dpp_move0;
   using wave::kDppWaveShl1;
   using wave::kDppWaveShr1;
@@ -103,18 +102,18 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
   int64_t gx = origin + x;
   if (gx >= n) gx -= n;
   const int64_t gidx = b * n + gx;
-  // this lane's outgoing slot entries (checkpoint bands in MODE 0, lambda
-  // bands in MODE 1): left side p = x, right side p = x - a + 1, one value
-  // per tier parity; a lane only stores where it owns a band point
-  double* const out = MODE == 0 ? ck_out : lam_slots;
-  double* const outL = out + sL + 2 * x;
-  double* const outR = out + sR + 2 * (x - kA + 1);
+  // this lane's outgoing lambda slot entries: left side p = x, right side
+  // p = x - a + 1, one value per tier parity; a lane only stores where it
+  // owns a band point
+  double* const outL = lam_slots + sL + 2 * x;
+  double* const outR = lam_slots + sR + 2 * (x - kA + 1);
 
   // ------------------------------------------------ forward recompute --
-  // MODE 1 keeps, for every tier d of the region, the Laplacian term of the
-  // dJ/dalpha sum at this lane's point, lap[d] = (u(x-1,d-1) + u(x+1,d-1)) -
-  // 2 u(x,d-1), formed from the same neighbour sum the update uses (IEEE
-  // addition commutes, so the bits equal those of the separate formula).
+  // The recompute keeps, for every tier d of the region, the Laplacian term
+  // of the dJ/dalpha sum at this lane's point, lap[d] = (u(x-1,d-1) +
+  // u(x+1,d-1)) - 2 u(x,d-1), formed from the same neighbour sum the update
+  // uses (IEEE addition commutes, so the bits equal those of the separate
+  // formula).
   double lap[2 * kH];
   double top = 0.0;  // the region's row at tier h
   double tipL = 0.0, tipR = 0.0;  // points -1 and w at tier h-1
@@ -137,49 +136,22 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
         hi = pick(lanes(1ull << (kW - 1)), tipR, hi);
       }
       const double sum = hi + lo;
-      if constexpr (MODE == 1) lap[t + 1] = sum - 2.0 * row;
+      lap[t + 1] = sum - 2.0 * row;
       row = k.fo * sum + k.c * row;  // heat_update(lo, row, hi)
     }
     top = row;
   }
   if constexpr (HL) {
     double row = top;
-    double c0 = 0.0, c1 = 0.0;  // MODE 0: this lane's outgoing band values, by tier parity
 #pragma unroll
-    for (int m = 0; m < kH; ++m) {
-      if (m > 0) {
-        const double lo = dpp_move0<kDppWaveShr1>(row), hi = dpp_move0<kDppWaveShl1>(row);
-        const double sum = hi + lo;
-        if constexpr (MODE == 1) lap[kH + m] = sum - 2.0 * row;
-        row = k.fo * sum + k.c * row;  // heat_update(lo, row, hi)
-      }
-      if constexpr (MODE == 0) {
-        // bands of Lambda tier m: [m, m+2) and [w-m-2, w-m).  Collected in
-        // registers and stored once: storing each tier's two-lane pieces as
-        // they form costs more in small writes than the selects.
-        const bool band = lanes(pair_bits(m) | pair_bits(kW - m - 2));
-        if (m & 1)
-          c1 = pick(band, row, c1);
-        else
-          c0 = pick(band, row, c0);
-      }
+    for (int m = 1; m < kH; ++m) {
+      const double lo = dpp_move0<kDppWaveShr1>(row), hi = dpp_move0<kDppWaveShl1>(row);
+      const double sum = hi + lo;
+      lap[kH + m] = sum - 2.0 * row;
+      row = k.fo * sum + k.c * row;  // heat_update(lo, row, hi)
     }
-    if constexpr (MODE == 0) {
-      // left side p = x at tiers m = x-1, x; right side p = x-a+1 at m = w-x-2, w-x-1
-      if (x <= kA) {
-        if (x <= kH - 1) outL[x & 1] = (x & 1) ? c1 : c0;
-        if (x >= 1) outL[(x - 1) & 1] = ((x - 1) & 1) ? c1 : c0;
-      }
-      if (x >= kA - 1) {
-        const int m0 = kW - x - 2, m1 = kW - x - 1;
-        if (m0 >= 0) outR[m0 & 1] = (m0 & 1) ? c1 : c0;
-        if (m1 <= kH - 1) outR[m1 & 1] = (m1 & 1) ? c1 : c0;
-      }
-    }
-  } else if constexpr (MODE == 0) {
-    uT[gidx] = top;
   }
-  if constexpr (MODE == 1) {
+  {
     // --------------------------------------------------- adjoint sweep --
     // lambda of later regions just outside Lambda tier h+m (m = 1 .. h):
     // [m-2, m) from the left slot (p = pos + 1), [w-m, w-m+2) from the right
@@ -253,6 +225,178 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
 #pragma unroll
     for (int s = kW / 2; s > 0; s >>= 1) acc = acc + __shfl_down(acc, s, kW);
     if (x == 0) partial[b * nt + j] += acc;
+  }
+}
+
+// Lane mask of register r when each lane holds P consecutive tile points and
+// a wave holds P tiles of 64 / P lanes: the lanes whose point l P + r is set
+// in `pos` (bit x = tile point x), in every tile of the wave.
+template <int P>
+__host__ __device__ constexpr uint64_t reg_bits(uint64_t pos, int r) {
+  uint64_t m = 0;
+  for (int l = 0; l < kW / P; ++l)
+    if ((pos >> (l * P + r)) & 1)
+      for (int tl = 0; tl < P; ++tl) m |= 1ull << (tl * (kW / P) + l);
+  return m;
+}
+
+// Lanes holding the first (last) point of a tile.
+template <int P>
+__host__ __device__ constexpr uint64_t tile_end_bits(bool last) {
+  uint64_t m = 0;
+  for (int tl = 0; tl < P; ++tl) m |= 1ull << (tl * (kW / P) + (last ? kW / P - 1 : 0));
+  return m;
+}
+
+// One heat tier over a lane's P points; lo and hi are the neighbours of its
+// first and last point.
+template <int P>
+__device__ __forceinline__ void fwd_update(double (&row)[P], double lo, double hi, const Consts<double>& k) {
+  double prev = lo;
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    const double nv = heat_update(prev, row[r], r + 1 < P ? row[r + 1] : hi, k);
+    prev = row[r];
+    row[r] = nv;
+  }
+}
+
+// V tiers T .. h-1 of the forward: insert the band values of tier T
+// ([a-T-2, a-T) and [a+T, a+T+2)) into the registers that hold them, then
+// compute tier T+1.  Tiers and registers are template arguments so that
+// every lane mask is a compile-time constant.
+template <int P, int T, int R>
+__device__ __forceinline__ void fwd_insert(double (&row)[P], const double (&bv0)[P], const double (&bv1)[P]) {
+  if constexpr (R < P) {
+    constexpr uint64_t m = reg_bits<P>(pair_bits(kA - T - 2) | pair_bits(kA + T), R);
+    if constexpr (m != 0) row[R] = wave::pick(wave::lanes(m), (T & 1) ? bv1[R] : bv0[R], row[R]);
+    fwd_insert<P, T, R + 1>(row, bv0, bv1);
+  }
+}
+
+template <int P, int T>
+__device__ __forceinline__ void fwd_v(double (&row)[P], const double (&bv0)[P], const double (&bv1)[P], double tipL,
+                                      double tipR, const Consts<double>& k) {
+  if constexpr (T < kH) {
+    fwd_insert<P, T, 0>(row, bv0, bv1);
+    double lo = wave::dpp_move0<wave::kDppWaveShr1>(row[P - 1]);
+    double hi = wave::dpp_move0<wave::kDppWaveShl1>(row[0]);
+    if constexpr (T == kH - 1) {
+      lo = wave::pick(wave::lanes(tile_end_bits<P>(false)), tipL, lo);
+      hi = wave::pick(wave::lanes(tile_end_bits<P>(true)), tipR, hi);
+    }
+    fwd_update<P>(row, lo, hi, k);
+    fwd_v<P, T + 1>(row, bv0, bv1, tipL, tipR, k);
+  }
+}
+
+// Lambda tiers M .. h-1: compute tier M (M > 0), then collect its bands
+// ([M, M+2) and [w-M-2, w-M)) by tier parity.
+template <int P, int M, int R>
+__device__ __forceinline__ void fwd_collect(const double (&row)[P], double (&c0)[P], double (&c1)[P]) {
+  if constexpr (R < P) {
+    constexpr uint64_t m = reg_bits<P>(pair_bits(M) | pair_bits(kW - M - 2), R);
+    if constexpr (m != 0) {
+      if constexpr (M & 1)
+        c1[R] = wave::pick(wave::lanes(m), row[R], c1[R]);
+      else
+        c0[R] = wave::pick(wave::lanes(m), row[R], c0[R]);
+      // select here, not at the stores: deferred selects keep every tier's row live
+      asm volatile("" : "+v"(c0[R]), "+v"(c1[R]));
+    }
+    fwd_collect<P, M, R + 1>(row, c0, c1);
+  }
+}
+
+template <int P, int M>
+__device__ __forceinline__ void fwd_l(double (&row)[P], double (&c0)[P], double (&c1)[P], const Consts<double>& k) {
+  if constexpr (M < kH) {
+    if constexpr (M > 0)
+      fwd_update<P>(row, wave::dpp_move0<wave::kDppWaveShr1>(row[P - 1]), wave::dpp_move0<wave::kDppWaveShl1>(row[0]),
+                    k);
+    fwd_collect<P, M, 0>(row, c0, c1);
+    fwd_l<P, M + 1>(row, c0, c1, k);
+  }
+}
+
+// Checkpointing forward phase: the regions, tiers and slot entries that the
+// reverse launch recomputes from, with P consecutive points per lane and P
+// tiles per wave.  The forward keeps no history, so a lane can hold several points:
+// its inner neighbours need no lane shift, and the two shifts per tier serve
+// P points instead of one.  Every point gets the same update from the same
+// three values, so the slots hold the same bits.
+template <int P, bool HV, bool HL>
+__global__ void __launch_bounds__(kW)
+forward_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const double* __restrict__ ck_in,
+               double* __restrict__ ck_out, const Consts<double>* __restrict__ kb, int64_t n, int64_t nt, int p) {
+  constexpr int LPT = kW / P;  // lanes per tile
+  const int lane = threadIdx.x;
+  const int l = lane % LPT;
+  const int64_t j = (int64_t)blockIdx.x * P + lane / LPT;  // tile
+  const bool valid = j < nt;
+  const int64_t jj = valid ? j : 0;  // tiles past the end read tile 0 and store nothing
+  const int64_t b = blockIdx.y;
+  const Consts<double> k = kb[b];
+  const int par = p & 1;
+  const int64_t origin = jj * kW + (par ? kA : 0);
+  const int64_t base = b * 2 * nt * kSL;
+  const int64_t sL = base + (par ? (nt + jj) * kSL : jj * kSL);
+  const int64_t sR = base + (par ? (jj + 1 == nt ? 0 : jj + 1) * kSL : (nt + jj) * kSL);
+  int64_t gidx[P];
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    int64_t gx = origin + l * P + r;
+    if (gx >= n) gx -= n;
+    gidx[r] = b * n + gx;
+  }
+
+  double row[P];
+  if constexpr (!HV) {
+#pragma unroll
+    for (int r = 0; r < P; ++r) row[r] = ustart[gidx[r]];
+  } else {
+    // incoming band values of this lane's points, one per tier parity
+    double bv0[P], bv1[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      const int x = l * P + r;
+      const int64_t src = x < kA ? sL + 2 * (x + 1) : sR + 2 * (x - kA);
+      bv0[r] = ck_in[src];
+      bv1[r] = ck_in[src + 1];
+      row[r] = 0.0;
+    }
+    const double tipL = ck_in[sL + ((kH - 1) & 1)];
+    const double tipR = ck_in[sR + 2 * (kW - kA) + ((kH - 1) & 1)];
+    fwd_v<P, 0>(row, bv0, bv1, tipL, tipR, k);
+  }
+  if constexpr (HL) {
+    double c0[P], c1[P];  // this lane's outgoing band values, by tier parity
+#pragma unroll
+    for (int r = 0; r < P; ++r) c0[r] = c1[r] = 0.0;
+    fwd_l<P, 0>(row, c0, c1, k);
+    if (valid) {
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        const int x = l * P + r;
+        // left side p = x at tiers m = x-1, x; right side p = x-a+1 at m = w-x-2, w-x-1
+        if (x <= kA) {
+          double* const outL = ck_out + sL + 2 * x;
+          if (x <= kH - 1) outL[x & 1] = (x & 1) ? c1[r] : c0[r];
+          if (x >= 1) outL[(x - 1) & 1] = ((x - 1) & 1) ? c1[r] : c0[r];
+        }
+        if (x >= kA - 1) {
+          double* const outR = ck_out + sR + 2 * (x - kA + 1);
+          const int m0 = kW - x - 2, m1 = kW - x - 1;
+          if (m0 >= 0) outR[m0 & 1] = (m0 & 1) ? c1[r] : c0[r];
+          if (m1 <= kH - 1) outR[m1 & 1] = (m1 & 1) ? c1[r] : c0[r];
+        }
+      }
+    }
+  } else {
+    if (valid) {
+#pragma unroll
+      for (int r = 0; r < P; ++r) uT[gidx[r]] = row[r];
+    }
   }
 }
 
@@ -449,10 +593,11 @@ int swept_forward_ckpt(swept_adjoint a, const void* u0, const double* alpha, voi
     for (int p = 0; p <= a->K && e == hipSuccess; ++p) {
       const double* ck_in = p > 0 ? a->ckpt + (size_t)(p - 1) * pslots : nullptr;
       double* ck_out = p < a->K ? a->ckpt + (size_t)p * pslots : nullptr;
-      auto kern = p == 0 ? swept::adj::region_kernel<0, false, true>
-                  : (p == a->K ? swept::adj::region_kernel<0, true, false> : swept::adj::region_kernel<0, true, true>);
-      hipLaunchKernelGGL(kern, dim3((unsigned)a->nt, (unsigned)a->batch), dim3(kW), 0, st, ur, static_cast<double*>(uT), ck_in,
-                         ck_out, nullptr, nullptr, nullptr, nullptr, k, a->n, a->nt, p);
+      constexpr int FP = swept::adj::kFwdPoints;
+      auto kern = p == 0 ? swept::adj::forward_kernel<FP, false, true>
+                  : (p == a->K ? swept::adj::forward_kernel<FP, true, false> : swept::adj::forward_kernel<FP, true, true>);
+      hipLaunchKernelGGL(kern, dim3((unsigned)((a->nt + FP - 1) / FP), (unsigned)a->batch), dim3(kW), 0, st, ur,
+                         static_cast<double*>(uT), ck_in, ck_out, k, a->n, a->nt, p);
       e = hipGetLastError();
     }
   }
@@ -484,9 +629,9 @@ int swept_adjoint_run(swept_adjoint a, const void* g_uT, void* g_u0, double* g_a
     const double* ur = a->rem + (size_t)a->r * total;
     for (int p = a->K; p >= 0 && e == hipSuccess; --p) {
       const double* ck_in = p > 0 ? a->ckpt + (size_t)(p - 1) * pslots : nullptr;
-      auto kern = p == 0 ? swept::adj::region_kernel<1, false, true>
-                  : (p == a->K ? swept::adj::region_kernel<1, true, false> : swept::adj::region_kernel<1, true, true>);
-      hipLaunchKernelGGL(kern, dim3((unsigned)a->nt, (unsigned)a->batch), dim3(kW), 0, st, ur, nullptr, ck_in, nullptr,
+      auto kern = p == 0 ? swept::adj::region_kernel<false, true>
+                  : (p == a->K ? swept::adj::region_kernel<true, false> : swept::adj::region_kernel<true, true>);
+      hipLaunchKernelGGL(kern, dim3((unsigned)a->nt, (unsigned)a->batch), dim3(kW), 0, st, ur, ck_in,
                          static_cast<const double*>(g_uT), a->lam_slots, lam_r, a->tiles, k, a->n, a->nt, p);
       e = hipGetLastError();
     }
