@@ -54,6 +54,7 @@ constexpr int kH = kW / (2 * kS);  // 16 tiers (8 steps) per full triangle
 constexpr int kA = kW / 2;         // inner seam
 constexpr int kSL = kW + 2 * kS;
 constexpr int kThreads = 256;
+constexpr int kFwdPoints = 4;  // points per lane (and tiles per wave) of the checkpointing forward
 
 // Coefficients of Jf(v)^T, formed on the host in FP64.
 struct JtCoef {
@@ -105,16 +106,207 @@ __host__ __device__ constexpr uint64_t outside_bits(int t) {
   return range_bits(kS * t - 2 * kS, kS * t) | range_bits(kW - kS * t, kW - kS * t + 2 * kS);
 }
 
-// One swept region of one tile in one wave64 (lane x = tile point x).
-// MODE 0: forward phase writing checkpoint slots (or u_T).  MODE 1: fused
-// adjoint (recompute, then the adjoint walk).  HV: the region has a V part
-// (every phase but the first); HL: it has a Lambda part (every phase but the
-// last).
-template <int MODE, bool HV, bool HL>
+// ---------------------------------------------------------------------------
+// Checkpointing forward with P consecutive points per lane and P tiles of 64
+// points per wave (64 / P lanes each).  It keeps no history beyond the last
+// even tier, so a lane can hold several points: only the two outermost
+// points on each side need lane shifts, and those serve P points.
+
+// Lane mask of register r: the lanes whose point l P + r is set in `pos`
+// (bit x = tile point x), in every tile of the wave.
+template <int P>
+__host__ __device__ constexpr uint64_t reg_bits(uint64_t pos, int r) {
+  uint64_t m = 0;
+  for (int l = 0; l < kW / P; ++l)
+    if ((pos >> (l * P + r)) & 1)
+      for (int tl = 0; tl < P; ++tl) m |= 1ull << (tl * (kW / P) + l);
+  return m;
+}
+
+// Lanes holding the first (last) points of a tile.
+template <int P>
+__host__ __device__ constexpr uint64_t tile_end_bits(bool last) {
+  uint64_t m = 0;
+  for (int tl = 0; tl < P; ++tl) m |= 1ull << (tl * (kW / P) + (last ? kW / P - 1 : 0));
+  return m;
+}
+
+// Points -2, -1 (lo) and P, P+1 (hi) around a lane's P points of a row.
+struct Halo {
+  double lo0, lo1, hi0, hi1;
+};
+
+template <int P>
+__device__ __forceinline__ Halo halo(const double (&row)[P]) {
+  using wave::dpp_move0;
+  return Halo{dpp_move0<wave::kDppWaveShr1>(row[P - 2]), dpp_move0<wave::kDppWaveShr1>(row[P - 1]),
+              dpp_move0<wave::kDppWaveShl1>(row[0]), dpp_move0<wave::kDppWaveShl1>(row[1])};
+}
+
+template <int P>
+__device__ __forceinline__ double at(const double (&row)[P], const Halo& h, int i) {
+  return i == -2 ? h.lo0 : (i == -1 ? h.lo1 : (i == P ? h.hi0 : (i == P + 1 ? h.hi1 : row[i])));
+}
+
+// Tier t+1 from tier t over a lane's points: the predictor (t+1 odd) or the
+// final stage with u at the previous even tier `ue`.
+template <int P, bool PRED>
+__device__ __forceinline__ void fwd_tier(double (&row)[P], const double (&ue)[P], const Halo& h,
+                                         const Consts<double>& k) {
+  double nv[P];
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    if constexpr (PRED)
+      nv[r] = ks_predictor(at<P>(row, h, r - 2), at<P>(row, h, r - 1), row[r], at<P>(row, h, r + 1),
+                           at<P>(row, h, r + 2), k);
+    else
+      nv[r] = ks_final(ue[r], at<P>(row, h, r - 2), at<P>(row, h, r - 1), row[r], at<P>(row, h, r + 1),
+                       at<P>(row, h, r + 2), k);
+  }
+#pragma unroll
+  for (int r = 0; r < P; ++r) row[r] = nv[r];
+}
+
+// V tiers T .. h-1: insert the bands of tier T ([a-4-2T, a-2T) and
+// [a+2T, a+2T+4)), keep u of the even tiers, compute tier T+1.  Tiers and
+// registers are template arguments so every lane mask is a constant.
+template <int P, int T, int R>
+__device__ __forceinline__ void fwd_insert(double (&row)[P], const double (&bv0)[P], const double (&bv1)[P]) {
+  if constexpr (R < P) {
+    constexpr uint64_t m = reg_bits<P>(range_bits(kA - 2 * kS - kS * T, kA - kS * T) |
+                                           range_bits(kA + kS * T, kA + kS * T + 2 * kS),
+                                       R);
+    if constexpr (m != 0) row[R] = wave::pick(lanes(m), (T & 1) ? bv1[R] : bv0[R], row[R]);
+    fwd_insert<P, T, R + 1>(row, bv0, bv1);
+  }
+}
+
+template <int P, int T>
+__device__ __forceinline__ void fwd_v(double (&row)[P], double (&ue)[P], const double (&bv0)[P],
+                                      const double (&bv1)[P], const Halo& tips, const Consts<double>& k) {
+  if constexpr (T < kH) {
+    fwd_insert<P, T, 0>(row, bv0, bv1);
+    if constexpr ((T & 1) == 0) {
+#pragma unroll
+      for (int r = 0; r < P; ++r) ue[r] = row[r];
+    }
+    Halo h = halo<P>(row);
+    if constexpr (T == kH - 1) {
+      // points -2, -1 and w, w+1 of tier h-1 come from the slots
+      const bool first = lanes(tile_end_bits<P>(false)), last = lanes(tile_end_bits<P>(true));
+      h.lo0 = wave::pick(first, tips.lo0, h.lo0);
+      h.lo1 = wave::pick(first, tips.lo1, h.lo1);
+      h.hi0 = wave::pick(last, tips.hi0, h.hi0);
+      h.hi1 = wave::pick(last, tips.hi1, h.hi1);
+    }
+    fwd_tier<P, ((T + 1) & 1) != 0>(row, ue, h, k);
+    fwd_v<P, T + 1>(row, ue, bv0, bv1, tips, k);
+  }
+}
+
+// Lambda tiers M .. h-1 (tier h + M of the region): compute tier M (M > 0),
+// then store its bands, [2M, 2M+4) to the left slot (p = x) and
+// [w-2M-4, w-2M) to the right slot (p = x - a + 2), from the lanes that own
+// them, one entry per tier parity.
+template <int P, int M, int R>
+__device__ __forceinline__ void fwd_store(const double (&row)[P], double* outL, double* outR, bool valid) {
+  if constexpr (R < P) {
+    constexpr uint64_t ml = reg_bits<P>(range_bits(kS * M, kS * M + 2 * kS), R);
+    constexpr uint64_t mr = reg_bits<P>(range_bits(kW - kS * M - 2 * kS, kW - kS * M), R);
+    if constexpr (ml != 0) {
+      if (valid && lanes(ml)) outL[2 * R + (M & 1)] = row[R];
+    }
+    if constexpr (mr != 0) {
+      if (valid && lanes(mr)) outR[2 * R + (M & 1)] = row[R];
+    }
+    fwd_store<P, M, R + 1>(row, outL, outR, valid);
+  }
+}
+
+template <int P, int M>
+__device__ __forceinline__ void fwd_l(double (&row)[P], double (&ue)[P], double* outL, double* outR, bool valid,
+                                      const Consts<double>& k) {
+  if constexpr (M < kH) {
+    if constexpr (M > 0) {
+      const Halo h = halo<P>(row);
+      fwd_tier<P, ((kH + M) & 1) != 0>(row, ue, h, k);
+      if constexpr (((kH + M) & 1) == 0) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) ue[r] = row[r];
+      }
+    }
+    fwd_store<P, M, 0>(row, outL, outR, valid);
+    fwd_l<P, M + 1>(row, ue, outL, outR, valid, k);
+  }
+}
+
+template <int P, bool HV, bool HL>
 __global__ void __launch_bounds__(kW)
-region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const double* __restrict__ ck_in,
-              double* __restrict__ ck_out, const double* __restrict__ gT, double* lam_slots,
-              double* __restrict__ g_ur, Consts<double> k, JtCoef c, int64_t n, int64_t nt, int p) {
+forward_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const double* __restrict__ ck_in,
+               double* __restrict__ ck_out, Consts<double> k, int64_t n, int64_t nt, int p) {
+  static_assert(P >= 2, "the lane shifts carry two points per side");
+  constexpr int LPT = kW / P;  // lanes per tile
+  const int lane = threadIdx.x;
+  const int l = lane % LPT;
+  const int64_t j = (int64_t)blockIdx.x * P + lane / LPT;  // tile
+  const bool valid = j < nt;
+  const int64_t jj = valid ? j : 0;  // tiles past the end read tile 0 and store nothing
+  const int64_t b = blockIdx.y;
+  const int par = p & 1;
+  const int64_t origin = jj * kW + (par ? kA : 0);
+  const int64_t base = b * 2 * nt * kSL;
+  const int64_t sL = base + (par ? (nt + jj) * kSL : jj * kSL);
+  const int64_t sR = base + (par ? (jj + 1 == nt ? 0 : jj + 1) * kSL : (nt + jj) * kSL);
+  int64_t gidx[P];
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    int64_t gx = origin + l * P + r;
+    if (gx >= n) gx -= n;
+    gidx[r] = b * n + gx;
+  }
+  double row[P], ue[P];
+  if constexpr (!HV) {
+#pragma unroll
+    for (int r = 0; r < P; ++r) row[r] = ustart[gidx[r]];
+  } else {
+    double bv0[P], bv1[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      const int x = l * P + r;
+      const int64_t src = x < kA ? sL + 2 * (x + kS) : sR + 2 * (x - kA);
+      bv0[r] = ck_in[src];
+      bv1[r] = ck_in[src + 1];
+      row[r] = 0.0;
+      ue[r] = 0.0;
+    }
+    // band points -2, -1, w, w+1 of tier h-1
+    constexpr int tp = (kH - 1) & 1;
+    const Halo tips{ck_in[sL + tp], ck_in[sL + 2 + tp], ck_in[sR + 2 * kA + tp], ck_in[sR + 2 * (kA + 1) + tp]};
+    fwd_v<P, 0>(row, ue, bv0, bv1, tips, k);
+  }
+  if constexpr (HL) {
+#pragma unroll
+    for (int r = 0; r < P; ++r) ue[r] = row[r];  // tier h is even
+    double* const outL = ck_out + sL + 2 * (l * P);
+    double* const outR = ck_out + sR + 2 * (l * P - kA + kS);
+    fwd_l<P, 0>(row, ue, outL, outR, valid, k);
+  } else {
+    if (valid) {
+#pragma unroll
+      for (int r = 0; r < P; ++r) uT[gidx[r]] = row[r];
+    }
+  }
+}
+
+// One swept region of one tile in one wave64 (lane x = tile point x).
+// The fused reverse launch of one phase: recompute the region, then walk the
+// adjoint down through it.  HV: the region has a V part (every phase but the
+// first); HL: it has a Lambda part (every phase but the last).
+template <bool HV, bool HL>
+__global__ void __launch_bounds__(kW)
+region_kernel(const double* __restrict__ ustart, const double* __restrict__ ck_in, const double* __restrict__ gT,
+              double* lam_slots, double* __restrict__ g_ur, Consts<double> k, JtCoef c, int64_t n, int64_t nt,
+              int p) {
   using wave::pick;
   const int x = threadIdx.x;
   const int64_t j = blockIdx.x;  // tile
@@ -129,15 +321,14 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
   const int64_t gidx = b * n + gx;
   // this lane's entry in the incoming slots (one value per tier parity)
   const int64_t src = x < kA ? sL + 2 * (x + kS) : sR + 2 * (x - kA);
-  // this lane's outgoing slot entries (checkpoint bands in MODE 0, adjoint
-  // bands in MODE 1): left side p = x, right side p = x - a + 2, one value
-  // per tier parity; a lane only stores where it owns a band point
-  double* const out = MODE == 0 ? ck_out : lam_slots;
-  double* const outL = out + sL + 2 * x;
-  double* const outR = out + sR + 2 * (x - kA + kS);
+  // this lane's outgoing adjoint slot entries: left side p = x, right side
+  // p = x - a + 2, one value per tier parity; a lane only stores where it
+  // owns a band point
+  double* const outL = lam_slots + sL + 2 * x;
+  double* const outR = lam_slots + sR + 2 * (x - kA + kS);
 
   // ------------------------------------------------ forward recompute --
-  double hist[2 * kH];  // u or q at (x, d), d = 0 .. 2h-1 (MODE 0 keeps only live tiers)
+  double hist[2 * kH];  // u or q at (x, d), d = 0 .. 2h-1
   if constexpr (!HV) {
     hist[kH] = ustart[gidx];
   } else {
@@ -174,18 +365,9 @@ region_kernel(const double* __restrict__ ustart, double* __restrict__ uT, const 
           row = ks_final(hist[kH + m - 2], nb.l2, nb.l1, row, nb.r1, nb.r2, k);
         hist[kH + m] = row;
       }
-      if constexpr (MODE == 0) {
-        // bands of Lambda tier m, stored by their lanes as they are formed:
-        // [2m, 2m+4) to the left side (p = x), [w-2m-4, w-2m) to the right
-        // side (p = x - a + 2), one entry per tier parity
-        if (lanes(range_bits(kS * m, kS * m + 2 * kS))) outL[m & 1] = row;
-        if (lanes(range_bits(kW - kS * m - 2 * kS, kW - kS * m))) outR[m & 1] = row;
-      }
     }
-  } else if constexpr (MODE == 0) {
-    uT[gidx] = hist[kH];
   }
-  if constexpr (MODE == 1) {
+  {
     // --------------------------------------------------- adjoint sweep --
     double in0 = 0.0, in1 = 0.0, ll0 = 0.0, ll1 = 0.0, lr0 = 0.0, lr1 = 0.0;
     if constexpr (HL) {
@@ -449,11 +631,12 @@ int swept_ks_forward_ckpt(swept_ks_adjoint a, const void* u0, void* uT, void* st
     for (int p = 0; p <= a->K && e == hipSuccess; ++p) {
       const double* ck_in = p > 0 ? a->ckpt + (size_t)(p - 1) * pslots : nullptr;
       double* ck_out = p < a->K ? a->ckpt + (size_t)p * pslots : nullptr;
-      auto kern = p == 0 ? swept::ksadj::region_kernel<0, false, true>
-                         : (p == a->K ? swept::ksadj::region_kernel<0, true, false>
-                                      : swept::ksadj::region_kernel<0, true, true>);
-      hipLaunchKernelGGL(kern, dim3((unsigned)a->nt, (unsigned)a->batch), dim3(kW), 0, st, ur, static_cast<double*>(uT),
-                         ck_in, ck_out, nullptr, nullptr, nullptr, a->k, a->c, a->n, a->nt, p);
+      constexpr int FP = swept::ksadj::kFwdPoints;
+      auto kern = p == 0 ? swept::ksadj::forward_kernel<FP, false, true>
+                         : (p == a->K ? swept::ksadj::forward_kernel<FP, true, false>
+                                      : swept::ksadj::forward_kernel<FP, true, true>);
+      hipLaunchKernelGGL(kern, dim3((unsigned)((a->nt + FP - 1) / FP), (unsigned)a->batch), dim3(kW), 0, st, ur,
+                         static_cast<double*>(uT), ck_in, ck_out, a->k, a->n, a->nt, p);
       e = hipGetLastError();
     }
   }
@@ -481,10 +664,10 @@ int swept_ks_adjoint_run(swept_ks_adjoint a, const void* g_uT, void* g_u0, void*
     const double* ur = a->rem + (size_t)a->r * total;
     for (int p = a->K; p >= 0 && e == hipSuccess; --p) {
       const double* ck_in = p > 0 ? a->ckpt + (size_t)(p - 1) * pslots : nullptr;
-      auto kern = p == 0 ? swept::ksadj::region_kernel<1, false, true>
-                         : (p == a->K ? swept::ksadj::region_kernel<1, true, false>
-                                      : swept::ksadj::region_kernel<1, true, true>);
-      hipLaunchKernelGGL(kern, dim3((unsigned)a->nt, (unsigned)a->batch), dim3(kW), 0, st, ur, nullptr, ck_in, nullptr,
+      auto kern = p == 0 ? swept::ksadj::region_kernel<false, true>
+                         : (p == a->K ? swept::ksadj::region_kernel<true, false>
+                                      : swept::ksadj::region_kernel<true, true>);
+      hipLaunchKernelGGL(kern, dim3((unsigned)a->nt, (unsigned)a->batch), dim3(kW), 0, st, ur, ck_in,
                          static_cast<const double*>(g_uT), a->lam_slots, lam_r, a->k, a->c, a->n, a->nt, p);
       e = hipGetLastError();
     }
