@@ -13,7 +13,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("n,steps", [(64, 5), (64, 32), (128, 45), (256, 96), (192, 101), (512, 333)])
+# n = 576 is 9 tiles: the 8-tile waves of the checkpointing forward end in a
+# wave holding one tile
+@pytest.mark.parametrize("n,steps", [(64, 5), (64, 32), (128, 45), (256, 96), (192, 101), (512, 333), (576, 70)])
 def test_adjoint_matches_cpu_reverse_sweep(n, steps):
     rng = np.random.default_rng(n * 1000 + steps)
     batch = 3
