@@ -111,9 +111,10 @@ region_kernel(const double* __restrict__ ustart, const double* __restrict__ ck_i
   // ------------------------------------------------ forward recompute --
   // The recompute keeps, for every tier d of the region, the Laplacian term
   // of the dJ/dalpha sum at this lane's point, lap[d] = (u(x-1,d-1) +
-  // u(x+1,d-1)) - 2 u(x,d-1), formed from the same neighbour sum the update
-  // uses (IEEE addition commutes, so the bits equal those of the separate
-  // formula).
+  // u(x+1,d-1)) - 2 u(x,d-1), formed from the neighbour sum the update uses.
+  // Only dJ/dalpha reads it, a sum that matches the reference to rounding
+  // rather than bit for bit, so it and the sum's terms use fused
+  // multiply-adds; lambda and dJ/du0 keep the plain update order.
   double lap[2 * kH];
   double top = 0.0;  // the region's row at tier h
   double tipL = 0.0, tipR = 0.0;  // points -1 and w at tier h-1
@@ -136,7 +137,7 @@ region_kernel(const double* __restrict__ ustart, const double* __restrict__ ck_i
         hi = pick(lanes(1ull << (kW - 1)), tipR, hi);
       }
       const double sum = hi + lo;
-      lap[t + 1] = sum - 2.0 * row;
+      lap[t + 1] = __builtin_fma(-2.0, row, sum);
       row = k.fo * sum + k.c * row;  // heat_update(lo, row, hi)
     }
     top = row;
@@ -147,7 +148,7 @@ region_kernel(const double* __restrict__ ustart, const double* __restrict__ ck_i
     for (int m = 1; m < kH; ++m) {
       const double lo = dpp_move0<kDppWaveShr1>(row), hi = dpp_move0<kDppWaveShl1>(row);
       const double sum = hi + lo;
-      lap[kH + m] = sum - 2.0 * row;
+      lap[kH + m] = __builtin_fma(-2.0, row, sum);
       row = k.fo * sum + k.c * row;  // heat_update(lo, row, hi)
     }
   }
@@ -182,7 +183,7 @@ region_kernel(const double* __restrict__ ustart, const double* __restrict__ ck_i
         lam = heat_update(lo, lam, hi, k);
       }
       if (HV || d != kH) {  // dJ/dalpha term lambda(x,d) (L u)(x, d-1)
-        acc = pick(lanes(row_bits(d)), acc + lam * lap[d], acc);
+        acc = pick(lanes(row_bits(d)), __builtin_fma(lam, lap[d], acc), acc);
         // settle this tier's sum here so that no term waits in a register
         asm volatile("" : "+v"(acc));
       }
