@@ -1,0 +1,60 @@
+"""Host-side checks of bench.py: it measures one GPU and refuses more, its
+ALU peak is the chip's FP64 vector rate without FMA, the traffic figure is
+read from the committed counter summary only while the kernel sources match
+it, and the flop counts per update are the stencils' operation counts."""
+import hashlib
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_alu_peak_is_fp64_lane_ops_without_fma():
+    # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one operation per lane per cycle
+    assert bench.ALU_PEAK_TFLOPS == pytest.approx(256 * 4 * 16 * 2.4e9 / 1e12)
+    assert bench.ALU_PEAK_TFLOPS == pytest.approx(78.6 / 2, rel=1e-3)
+
+
+def test_flops_per_update():
+    # heat: fo*(r+l) + c*o is 4 operations; a KS sub-step is the 5-point
+    # right-hand side (18 operations, the two squares included) plus the
+    # axpy (2), 20 in all
+    assert bench.FLOPS_PER_TIER_UPDATE["heat"] == 4
+    assert bench.FLOPS_PER_TIER_UPDATE["heat_insulated"] == 4
+    assert bench.FLOPS_PER_TIER_UPDATE["ks"] == 20
+
+
+def test_traffic_read_only_for_matching_sources(tmp_path, monkeypatch):
+    wl = {"kind": "heat", "dtype": "f64", "n": 2 ** 20}
+    t = bench._traffic_from_profile(wl, 1024, "compact")
+    assert t is not None and 3.0e7 < t < 4.0e7  # both 1026-value slots of 1024 tiles, read and written
+    # other workloads or widths have no committed counters
+    assert bench._traffic_from_profile({"kind": "ks", "dtype": "f64", "n": 2 ** 20}, 1024, "compact") is None
+    assert bench._traffic_from_profile(wl, 512, "compact") is None
+    # a changed kernel source voids the figure
+    src = os.path.join(ROOT, bench.KERNEL_SOURCES["compact"][0])
+    real = open(src, "rb").read()
+    fake_root = tmp_path
+    for f in bench.KERNEL_SOURCES["compact"]:
+        dst = fake_root / f
+        dst.parent.mkdir(parents=True, exist_ok=True)
+        dst.write_bytes(open(os.path.join(ROOT, f), "rb").read())
+    (fake_root / bench.KERNEL_SOURCES["compact"][0]).write_bytes(real + b"\n// changed\n")
+    prof = fake_root / bench.TRAFFIC_SUMMARY["compact"]
+    prof.parent.mkdir(parents=True, exist_ok=True)
+    prof.write_bytes(open(os.path.join(ROOT, bench.TRAFFIC_SUMMARY["compact"]), "rb").read())
+    monkeypatch.setattr(bench, "ROOT", str(fake_root))
+    assert bench._traffic_from_profile(wl, 1024, "compact") is None
+    assert hashlib.sha256(real).hexdigest()  # the real tree is untouched
