@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import paper_1612_02495_amd as P
-from paper_1612_02495_amd import Plan, inputs
+from paper_1612_02495_amd import Plan
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
