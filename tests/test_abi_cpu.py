@@ -36,6 +36,22 @@ def test_header_declares_the_boundary():
         assert n in names
 
 
+def test_header_is_plain_c(tmp_path):
+    # the boundary takes plain pointers and sizes: the header compiles as
+    # C99 with no warnings, and a C program can call every entry point
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    calls = "\n".join(f"  (void)&{n};" for n in _declared_functions())
+    src.write_text(f'#include "swept.h"\nint main(void) {{\n{calls}\n  return 0;\n}}\n')
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.dirname(HEADER),
+                        "-fsyntax-only", str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def _create(n=1024, kind=0, dtype=1, dt=1e-6, dx=1e-3, alpha=1.0, w=64, spc=0):
     h = ctypes.c_void_p()
     rc = _lib.lib().swept_plan_create(ctypes.byref(h), n, kind, dtype, dt, dx, alpha, w, spc)
