@@ -293,16 +293,17 @@ def run_batch(args, wl):
 
 
 CSRC = "paper_1612_02495_amd/csrc/"
-# Per engine: the sources that define its diamond kernel, and the committed
-# rocprofv3 counter summary for the heat FP64 N=2^20 w=1024 workload.
+# Per engine: the sources that define its diamond kernel; per (kind, engine):
+# the committed rocprofv3 counter summary of the FP64 N=2^20 w=1024 workload.
 KERNEL_SOURCES = {
     "wave": [CSRC + "phase_wave.hip", CSRC + "stencil.h", CSRC + "internal.h"],
     "compact": [CSRC + "phase_compact.hip", CSRC + "compact_tile.h", CSRC + "wave_tile.h", CSRC + "stencil.h",
                 CSRC + "internal.h"],
 }
 TRAFFIC_SUMMARY = {
-    "wave": "profiles/phase_wave_heat_f64_n2p20_w1024_pmc.md",
-    "compact": "profiles/phase_compact_heat_f64_n2p20_w1024_pmc.md",
+    ("heat", "wave"): "profiles/phase_wave_heat_f64_n2p20_w1024_pmc.md",
+    ("heat", "compact"): "profiles/phase_compact_heat_f64_n2p20_w1024_pmc.md",
+    ("ks", "compact"): "profiles/phase_compact_ks_f64_n2p20_w1024_pmc.md",
 }
 
 
@@ -313,10 +314,10 @@ def _traffic_from_profile(wl, tile, engine):
     import hashlib
     if engine == "auto":  # the library's AUTO choice for these widths
         engine = "compact" if tile in (512, 1024) else "wave"
-    if not (wl["kind"] == "heat" and wl["dtype"] == "f64" and wl["n"] == 2 ** 20 and tile == 1024
-            and engine in TRAFFIC_SUMMARY):
+    key = (wl["kind"], engine)
+    if not (wl["dtype"] == "f64" and wl["n"] == 2 ** 20 and tile == 1024 and key in TRAFFIC_SUMMARY):
         return None
-    path = os.path.join(ROOT, TRAFFIC_SUMMARY[engine])
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY[key])
     if not os.path.exists(path):
         return None
     fields = {}
