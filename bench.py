@@ -293,17 +293,19 @@ def run_batch(args, wl):
 
 
 CSRC = "paper_1612_02495_amd/csrc/"
-# Per engine: the sources that define its diamond kernel; per (kind, engine):
-# the committed rocprofv3 counter summary of the FP64 N=2^20 w=1024 workload.
+# Per engine: the sources that define its diamond kernel; per (kind, dtype,
+# engine): the committed rocprofv3 counter summary of the N=2^20 w=1024 workload.
 KERNEL_SOURCES = {
     "wave": [CSRC + "phase_wave.hip", CSRC + "stencil.h", CSRC + "internal.h"],
     "compact": [CSRC + "phase_compact.hip", CSRC + "compact_tile.h", CSRC + "wave_tile.h", CSRC + "stencil.h",
                 CSRC + "internal.h"],
 }
 TRAFFIC_SUMMARY = {
-    ("heat", "wave"): "profiles/phase_wave_heat_f64_n2p20_w1024_pmc.md",
-    ("heat", "compact"): "profiles/phase_compact_heat_f64_n2p20_w1024_pmc.md",
-    ("ks", "compact"): "profiles/phase_compact_ks_f64_n2p20_w1024_pmc.md",
+    ("heat", "f64", "wave"): "profiles/phase_wave_heat_f64_n2p20_w1024_pmc.md",
+    ("heat", "f64", "compact"): "profiles/phase_compact_heat_f64_n2p20_w1024_pmc.md",
+    ("heat", "f32", "compact"): "profiles/phase_compact_heat_f32_n2p20_w1024_pmc.md",
+    ("heat_insulated", "f64", "compact"): "profiles/phase_compact_heat_insulated_f64_n2p20_w1024_pmc.md",
+    ("ks", "f64", "compact"): "profiles/phase_compact_ks_f64_n2p20_w1024_pmc.md",
 }
 
 
@@ -314,8 +316,8 @@ def _traffic_from_profile(wl, tile, engine):
     import hashlib
     if engine == "auto":  # the library's AUTO choice for these widths
         engine = "compact" if tile in (512, 1024) else "wave"
-    key = (wl["kind"], engine)
-    if not (wl["dtype"] == "f64" and wl["n"] == 2 ** 20 and tile == 1024 and key in TRAFFIC_SUMMARY):
+    key = (wl["kind"], wl["dtype"], engine)
+    if not (wl["n"] == 2 ** 20 and tile == 1024 and key in TRAFFIC_SUMMARY):
         return None
     path = os.path.join(ROOT, TRAFFIC_SUMMARY[key])
     if not os.path.exists(path):

@@ -42,7 +42,7 @@ def test_traffic_read_only_for_matching_sources(tmp_path, monkeypatch):
     assert t is not None and 3.0e7 < t < 4.0e7  # both 1026-value slots of 1024 tiles, read and written
     # other sizes, widths or precisions have no committed counters
     assert bench._traffic_from_profile({"kind": "heat", "dtype": "f64", "n": 2 ** 21}, 1024, "compact") is None
-    assert bench._traffic_from_profile({"kind": "heat", "dtype": "f32", "n": 2 ** 20}, 1024, "compact") is None
+    assert bench._traffic_from_profile({"kind": "ks", "dtype": "f32", "n": 2 ** 20}, 1024, "compact") is None
     assert bench._traffic_from_profile(wl, 512, "compact") is None
     # a changed kernel source voids the figure
     src = os.path.join(ROOT, bench.KERNEL_SOURCES["compact"][0])
@@ -53,9 +53,9 @@ def test_traffic_read_only_for_matching_sources(tmp_path, monkeypatch):
         dst.parent.mkdir(parents=True, exist_ok=True)
         dst.write_bytes(open(os.path.join(ROOT, f), "rb").read())
     (fake_root / bench.KERNEL_SOURCES["compact"][0]).write_bytes(real + b"\n// changed\n")
-    prof = fake_root / bench.TRAFFIC_SUMMARY[("heat", "compact")]
+    prof = fake_root / bench.TRAFFIC_SUMMARY[("heat", "f64", "compact")]
     prof.parent.mkdir(parents=True, exist_ok=True)
-    prof.write_bytes(open(os.path.join(ROOT, bench.TRAFFIC_SUMMARY[("heat", "compact")]), "rb").read())
+    prof.write_bytes(open(os.path.join(ROOT, bench.TRAFFIC_SUMMARY[("heat", "f64", "compact")]), "rb").read())
     monkeypatch.setattr(bench, "ROOT", str(fake_root))
     assert bench._traffic_from_profile(wl, 1024, "compact") is None
     assert hashlib.sha256(real).hexdigest()  # the real tree is untouched
