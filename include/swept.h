@@ -135,6 +135,29 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
 int swept_run(swept_plan p, void* u, int64_t steps, void* stream);
 
 /*
+ * swept_run_noalloc -- swept_run without a plan, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments n .. steps_per_cycle are those
+ * of swept_plan_create and are validated the same way, except that
+ * tile_width = 0 takes the default width (the largest power of two up to 1024
+ * dividing n) and never the autotuner's table; u, steps and stream are those
+ * of swept_run, and the result is the same, bit for bit.  Nothing is
+ * allocated: the edge slots live in a static array in the library's device
+ * memory, 32 MiB per GPU (held by each GPU the library runs on until the
+ * process ends; its address is looked up on the first call on each device).
+ * A grid whose edge slots need more, 2 (n / tile_width) (tile_width + 2 s)
+ * values (about 16 bytes per point in FP64, so n up to about 2^21 at tile
+ * width 1024), fails with EUNSUPPORTED before anything is launched.  Every call
+ * on one GPU uses that GPU's one array, and nothing in it needs to start at
+ * zero (each phase writes every slot entry before the next phase reads it);
+ * calls that overlap on one GPU (on two streams, or from two threads) race on
+ * it and must be serialised by the caller.  The current HIP device is the
+ * device the call runs on.
+ */
+int swept_run_noalloc(int64_t n, int kind, int dtype, double dt, double dx, double alpha, int tile_width,
+                      int steps_per_cycle, void* u, int64_t steps, void* stream);
+
+/*
  * naive_run -- the classic decomposition (Sec. 4.4): one kernel launch per
  * sub-timestep reading and writing global memory, ping-ponging with the
  * plan's buffer.  Same arguments and result as swept_run.

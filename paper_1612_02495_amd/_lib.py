@@ -53,6 +53,7 @@ def _declare(lib):
     lib.swept_plan_create.argtypes = [ctypes.POINTER(vp), i64, i32, i32, dbl, dbl, dbl, i32, i32]
     lib.swept_run.argtypes = [vp, vp, i64, vp]
     lib.naive_run.argtypes = [vp, vp, i64, vp]
+    lib.swept_run_noalloc.argtypes = [i64, i32, i32, dbl, dbl, dbl, i32, i32, vp, i64, vp]
     lib.swept_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(sz)]
     lib.swept_plan_set_engine.argtypes = [vp, i32]
     lib.swept_plan_destroy.argtypes = [vp]
@@ -90,7 +91,7 @@ def _declare(lib):
     lib.swept_ks_adjoint_destroy.restype = None
     for name in ("swept_ks_adjoint_create", "swept_ks_forward_ckpt", "swept_ks_adjoint_run",
                  "swept_ks_adjoint_info", "swept_adjoint_create", "swept_forward_ckpt", "swept_adjoint_run", "swept_adjoint_info",
-                 "swept_batch_create", "swept_batch_run", "swept_batch_set_engine", "swept_batch_info", "swept_autotune", "swept_autotune_lookup", "swept_tile_geometry", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
+                 "swept_batch_create", "swept_batch_run", "swept_batch_set_engine", "swept_batch_info", "swept_autotune", "swept_autotune_lookup", "swept_tile_geometry", "swept_plan_create", "swept_run", "swept_run_noalloc", "naive_run", "swept_plan_info",
                  "swept_plan_set_engine", "swept_schedule"):
         getattr(lib, name).restype = i32
     return lib

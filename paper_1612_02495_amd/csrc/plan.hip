@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -13,6 +14,14 @@
 
 using swept::Consts;
 using swept::PhaseArgs;
+
+// Edge slots of swept_run_noalloc: one array per device, in the code object's
+// device memory, held by each GPU the library runs on until the process ends.
+// Host code never uses its name as an address (on the host it is a stand-in
+// symbol): the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current.
+static constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
 
 namespace {
 
@@ -48,7 +57,7 @@ constexpr int kMaxTile = 4096;
 
 // Tile width rules: w = 2s * (tiers of a full triangle); KS phases must end
 // on whole timesteps (predictor + final), so w/4 has to be even.
-bool tile_ok(int kind, int w, std::string* why) {
+bool tile_ok(int kind, int w, const char** why) {
   const int s = radius_of(kind);
   if (w < kMinTile || w > kMaxTile) {
     *why = "tile_width must lie in [4, 4096]";
@@ -195,7 +204,7 @@ hipError_t run_naive(const swept_plan_s* p, T* u, int64_t steps, const Consts<T>
 int choose_tile(int kind, int64_t n) {
   // Largest power of two up to 1024 that divides n (the automatic tuner of
   // the benchmark refines this per workload).
-  std::string why;
+  const char* why = "";
   for (int w = 1024; w >= kMinTile; w >>= 1) {
     if (n % w == 0 && n >= w && tile_ok(kind, w, &why) &&
         (kind != SWEPT_HEAT_INSULATED || engine_supports(SWEPT_ENGINE_COMPACT, kind, w)))
@@ -204,48 +213,12 @@ int choose_tile(int kind, int64_t n) {
   return 0;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* swept_last_error(void) { return g_last_error.c_str(); }
-
-int swept_schedule(int kind, int tile_width, int steps_per_cycle, int64_t steps, int32_t* heights,
-                   int64_t cap, int64_t* count) {
-  if (!valid_kind(kind)) return fail(SWEPT_EINVAL, "unknown stencil kind");
-  std::string why;
-  if (!tile_ok(kind, tile_width, &why)) return fail(SWEPT_EINVAL, why);
-  const int hfull = full_tiers(kind, tile_width);
-  const int tps = tiers_per_step(kind);
-  if (steps_per_cycle < 0 || steps_per_cycle * tps > hfull)
-    return fail(SWEPT_EINVAL, "steps_per_cycle exceeds the triangle height of this tile width");
-  if (steps < 0) return fail(SWEPT_EINVAL, "steps must be >= 0");
-  if (!count) return fail(SWEPT_EINVAL, "count must not be NULL");
-  if (cap < 0 || (cap > 0 && !heights)) return fail(SWEPT_EINVAL, "heights must hold cap entries");
-  const int h = steps_per_cycle ? steps_per_cycle * tps : hfull;
-  std::vector<int32_t> e;
-  make_schedule(h, steps * tps, &e);
-  for (int64_t i = 0; i < cap && i < (int64_t)e.size(); ++i) heights[i] = e[(size_t)i];
-  *count = (int64_t)e.size();
-  return SWEPT_OK;
-}
-
-int swept_tile_geometry(int kind, int tile_width, int* full_tiers_out, int* row_values,
-                        int* edge_slot_values) {
-  if (!valid_kind(kind)) return fail(SWEPT_EINVAL, "unknown stencil kind");
-  std::string why;
-  if (!tile_ok(kind, tile_width, &why)) return fail(SWEPT_EINVAL, why);
-  const int s = radius_of(kind);
-  if (full_tiers_out) *full_tiers_out = full_tiers(kind, tile_width);
-  if (row_values) *row_values = tile_width + 2 * s;
-  if (edge_slot_values) *edge_slot_values = swept::slot_values(tile_width, s);
-  return SWEPT_OK;
-}
-
-int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt, double dx, double alpha,
-                      int tile_width, int steps_per_cycle) {
-  if (!out) return fail(SWEPT_EINVAL, "out must not be NULL");
-  *out = nullptr;
+// Validate a plan request and fill in its geometry, constants, engine and
+// workspace size, allocating nothing (the device is only queried).  With
+// use_tuned, tile_width = 0 and steps_per_cycle = 0 take the autotuner's
+// remembered configuration when there is one.
+int plan_setup(swept_plan_s* p, int64_t n, int kind, int dtype, double dt, double dx, double alpha, int tile_width,
+               int steps_per_cycle, bool use_tuned, size_t max_slot_bytes) {
   if (!valid_kind(kind)) return fail(SWEPT_EINVAL, "unknown stencil kind");
   if (dtype != SWEPT_F32 && dtype != SWEPT_F64) return fail(SWEPT_EINVAL, "unknown dtype");
   if (n < kMinTile) return fail(SWEPT_EINVAL, "n must be >= 4");
@@ -253,13 +226,13 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
   if (kind != SWEPT_KS_RK2 && !is_finite(alpha)) return fail(SWEPT_EINVAL, "alpha must be finite");
   if (tile_width < 0) return fail(SWEPT_EINVAL, "tile_width must be >= 0");
   int w = tile_width;
-  std::string why;
+  const char* why = "";
   int tuned_engine = SWEPT_ENGINE_AUTO;
   if (w == 0) {
     // tuned configuration for this (kind, dtype, n) if the autotuner has one
     swept::TuneEntry te;
-    if (steps_per_cycle == 0 && swept::tune_lookup(kind, dtype, n, &te) && tile_ok(kind, te.tile_width, &why) &&
-        n % te.tile_width == 0 && te.steps_per_cycle >= 0 &&
+    if (use_tuned && steps_per_cycle == 0 && swept::tune_lookup(kind, dtype, n, &te) &&
+        tile_ok(kind, te.tile_width, &why) && n % te.tile_width == 0 && te.steps_per_cycle >= 0 &&
         te.steps_per_cycle * tiers_per_step(kind) <= full_tiers(kind, te.tile_width) &&
         engine_supports(te.engine, kind, te.tile_width)) {
       w = te.tile_width;
@@ -280,8 +253,7 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
   if (steps_per_cycle < 0 || steps_per_cycle * tps > hfull)
     return fail(SWEPT_EINVAL, "steps_per_cycle exceeds the triangle height of this tile width");
 
-  auto* p = new (std::nothrow) swept_plan_s();
-  if (!p) return fail(SWEPT_ENOMEM, "host allocation failed");
+  *p = swept_plan_s();
   p->n = n;
   p->kind = kind;
   p->dtype = dtype;
@@ -306,17 +278,16 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
   p->kf.dt = (float)p->kd.dt;
   p->kf.dth = (float)p->kd.dth;
 
+  p->slots_bytes = (size_t)(2 * p->nt) * (size_t)swept::slot_values(w, p->s) * elem_size(dtype);
+  if (max_slot_bytes && p->slots_bytes > max_slot_bytes)
+    return fail(SWEPT_EUNSUPPORTED, "the edge slots of this grid need " + std::to_string(p->slots_bytes) +
+                                        " bytes; the static workspace holds " + std::to_string(max_slot_bytes));
+
   hipError_t e = hipGetDevice(&p->device);
-  if (e != hipSuccess) {
-    delete p;
-    return hip_fail(e, "hipGetDevice");
-  }
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   int max_lds = 0;
   e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
-  if (e != hipSuccess) {
-    delete p;
-    return hip_fail(e, "hipDeviceGetAttribute");
-  }
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
   size_t lds = 0;
   if (kind != SWEPT_KS_RK2)
     lds = dtype == SWEPT_F64 ? swept::phase_lds_bytes<swept::kHeat, double>(w)
@@ -324,24 +295,111 @@ int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt
   else
     lds = dtype == SWEPT_F64 ? swept::phase_lds_bytes<swept::kKS, double>(w)
                              : swept::phase_lds_bytes<swept::kKS, float>(w);
-  if (lds > (size_t)max_lds && !swept::wave_engine_supports(stencil_of(kind), w)) {
-    delete p;
+  if (lds > (size_t)max_lds && !swept::wave_engine_supports(stencil_of(kind), w))
     return fail(SWEPT_EUNSUPPORTED, "tile too wide for the LDS of this device");
-  }
   p->engine = tuned_engine;
   p->lds_fits = lds <= (size_t)max_lds;
   // a tuned LDS choice that this device's LDS cannot hold falls back to AUTO
   // (a register engine: the width check above guarantees one exists)
   if (!p->lds_fits && p->engine == SWEPT_ENGINE_LDS) p->engine = SWEPT_ENGINE_AUTO;
-  if (!launch_fits(p->engine, kind, w, p->nt)) {
-    delete p;
-    return fail(SWEPT_EUNSUPPORTED, kTooManyTiles);
+  if (!launch_fits(p->engine, kind, w, p->nt)) return fail(SWEPT_EUNSUPPORTED, kTooManyTiles);
+  return SWEPT_OK;
+}
+
+// Enqueue the launches of one swept run of p on st with `slots` as the edge
+// slots: an up-triangle phase, the diamond phases and a down-triangle phase;
+// full phases of p->h tiers, the remainder last.  Nothing is allocated.
+int enqueue_swept(const swept_plan_s* p, void* slots, void* u, int64_t steps, hipStream_t st) {
+  const int64_t tiers = steps * tiers_per_step(p->kind);
+  const int64_t full = tiers / p->h;
+  const int rem = (int)(tiers % p->h);
+  const int64_t nedge = full + (rem ? 1 : 0);  // edge sets; phases = nedge + 1
+  for (int64_t i = 0; i <= nedge; ++i) {
+    PhaseArgs a;
+    a.u = u;
+    a.slots = slots;
+    a.n = p->n;
+    a.w = p->w;
+    a.nt = p->nt;
+    a.parity = (int)(i & 1);
+    a.hv = i == 0 ? 0 : (i - 1 < full ? p->h : rem);
+    a.hl = i == nedge ? 0 : (i < full ? p->h : rem);
+    hipError_t err = p->dtype == SWEPT_F64 ? dispatch_phase<double>(p, a, p->kd, st)
+                                           : dispatch_phase<float>(p, a, p->kf, st);
+    if (err != hipSuccess) return hip_fail(err, "swept phase launch");
   }
-  const size_t es = elem_size(dtype);
-  p->slots_bytes = (size_t)(2 * p->nt) * (size_t)swept::slot_values(w, p->s) * es;
+  return SWEPT_OK;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be current: looked up
+// on the first call for that device, then remembered.
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(SWEPT_EUNSUPPORTED, "device index beyond the static workspace table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SWEPT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* swept_last_error(void) { return g_last_error.c_str(); }
+
+int swept_schedule(int kind, int tile_width, int steps_per_cycle, int64_t steps, int32_t* heights,
+                   int64_t cap, int64_t* count) {
+  if (!valid_kind(kind)) return fail(SWEPT_EINVAL, "unknown stencil kind");
+  const char* why = "";
+  if (!tile_ok(kind, tile_width, &why)) return fail(SWEPT_EINVAL, why);
+  const int hfull = full_tiers(kind, tile_width);
+  const int tps = tiers_per_step(kind);
+  if (steps_per_cycle < 0 || steps_per_cycle * tps > hfull)
+    return fail(SWEPT_EINVAL, "steps_per_cycle exceeds the triangle height of this tile width");
+  if (steps < 0) return fail(SWEPT_EINVAL, "steps must be >= 0");
+  if (!count) return fail(SWEPT_EINVAL, "count must not be NULL");
+  if (cap < 0 || (cap > 0 && !heights)) return fail(SWEPT_EINVAL, "heights must hold cap entries");
+  const int h = steps_per_cycle ? steps_per_cycle * tps : hfull;
+  std::vector<int32_t> e;
+  make_schedule(h, steps * tps, &e);
+  for (int64_t i = 0; i < cap && i < (int64_t)e.size(); ++i) heights[i] = e[(size_t)i];
+  *count = (int64_t)e.size();
+  return SWEPT_OK;
+}
+
+int swept_tile_geometry(int kind, int tile_width, int* full_tiers_out, int* row_values,
+                        int* edge_slot_values) {
+  if (!valid_kind(kind)) return fail(SWEPT_EINVAL, "unknown stencil kind");
+  const char* why = "";
+  if (!tile_ok(kind, tile_width, &why)) return fail(SWEPT_EINVAL, why);
+  const int s = radius_of(kind);
+  if (full_tiers_out) *full_tiers_out = full_tiers(kind, tile_width);
+  if (row_values) *row_values = tile_width + 2 * s;
+  if (edge_slot_values) *edge_slot_values = swept::slot_values(tile_width, s);
+  return SWEPT_OK;
+}
+
+int swept_plan_create(swept_plan* out, int64_t n, int kind, int dtype, double dt, double dx, double alpha,
+                      int tile_width, int steps_per_cycle) {
+  if (!out) return fail(SWEPT_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  swept_plan_s cfg;
+  int rc = plan_setup(&cfg, n, kind, dtype, dt, dx, alpha, tile_width, steps_per_cycle, true, 0);
+  if (rc != SWEPT_OK) return rc;
+  auto* p = new (std::nothrow) swept_plan_s(cfg);
+  if (!p) return fail(SWEPT_ENOMEM, "host allocation failed");
   p->poison = swept::debug_poison_requested();
-  p->buf_bytes = (size_t)n * es;
-  e = hipMalloc(&p->slots, p->slots_bytes);
+  p->buf_bytes = (size_t)n * elem_size(dtype);
+  hipError_t e = hipMalloc(&p->slots, p->slots_bytes);
   if (e != hipSuccess) {
     delete p;
     return fail(SWEPT_ENOMEM, std::string("hipMalloc(edge slots): ") + hipGetErrorString(e));
@@ -393,8 +451,6 @@ int swept_run(swept_plan p, void* u, int64_t steps, void* stream) {
   if (steps < 0) return fail(SWEPT_EINVAL, "steps must be >= 0");
   if (steps == 0) return SWEPT_OK;
   if (!u) return fail(SWEPT_EINVAL, "u must not be NULL");
-  std::vector<int32_t> e;
-  make_schedule(p->h, steps * tiers_per_step(p->kind), &e);
   swept::DeviceGuard g(p->device);
   if (!g.ok) return hip_fail(g.err, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -402,22 +458,26 @@ int swept_run(swept_plan p, void* u, int64_t steps, void* stream) {
     const hipError_t pe = swept::poison_fill(p->slots, p->slots_bytes, (int)elem_size(p->dtype), st);
     if (pe != hipSuccess) return hip_fail(pe, "workspace poison fill");
   }
-  const int64_t nphase = (int64_t)e.size() + 1;
-  for (int64_t i = 0; i < nphase; ++i) {
-    PhaseArgs a;
-    a.u = u;
-    a.slots = p->slots;
-    a.n = p->n;
-    a.w = p->w;
-    a.nt = p->nt;
-    a.parity = (int)(i & 1);
-    a.hv = i == 0 ? 0 : e[(size_t)(i - 1)];
-    a.hl = i == nphase - 1 ? 0 : e[(size_t)i];
-    hipError_t err = p->dtype == SWEPT_F64 ? dispatch_phase<double>(p, a, p->kd, st)
-                                           : dispatch_phase<float>(p, a, p->kf, st);
-    if (err != hipSuccess) return hip_fail(err, "swept phase launch");
+  return enqueue_swept(p, p->slots, u, steps, st);
+}
+
+int swept_run_noalloc(int64_t n, int kind, int dtype, double dt, double dx, double alpha, int tile_width,
+                      int steps_per_cycle, void* u, int64_t steps, void* stream) {
+  if (steps < 0) return fail(SWEPT_EINVAL, "steps must be >= 0");
+  if (steps > 0 && !u) return fail(SWEPT_EINVAL, "u must not be NULL");
+  swept_plan_s p;
+  int rc = plan_setup(&p, n, kind, dtype, dt, dx, alpha, tile_width, steps_per_cycle, false, kScratchBytes);
+  if (rc != SWEPT_OK) return rc;
+  if (steps == 0) return SWEPT_OK;
+  void* slots = nullptr;
+  rc = scratch_address(p.device, &slots);
+  if (rc != SWEPT_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (swept::debug_poison_requested()) {
+    const hipError_t pe = swept::poison_fill(slots, p.slots_bytes, (int)elem_size(p.dtype), st);
+    if (pe != hipSuccess) return hip_fail(pe, "workspace poison fill");
   }
-  return SWEPT_OK;
+  return enqueue_swept(&p, slots, u, steps, st);
 }
 
 int naive_run(swept_plan p, void* u, int64_t steps, void* stream) {
@@ -465,7 +525,7 @@ int swept_autotune(int64_t n, int kind, int dtype, double dt, double dx, double 
     int w, spc, engine;
   };
   std::vector<Cand> cands;
-  std::string why;
+  const char* why = "";
   for (int w = 64; w <= 2048; w <<= 1) {
     if (n % w != 0 || n < w || !tile_ok(kind, w, &why)) continue;
     const int full_steps = full_tiers(kind, w) / tps;

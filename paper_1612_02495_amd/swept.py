@@ -54,6 +54,15 @@ def swept_run(plan, u, steps: int, stream=None) -> None:
     check(_lib.lib().swept_run(plan, ctypes.c_void_p(u.data_ptr()), int(steps), _stream_ptr(u, stream)))
 
 
+def swept_run_noalloc(n: int, kind, dtype, dt: float, dx: float, alpha: float, tile_width: int,
+                      steps_per_cycle: int, u, steps: int, stream=None) -> None:
+    """swept_run without a plan: the edge slots live in the library's static
+    per-device array, so the call allocates no device memory."""
+    check(_lib.lib().swept_run_noalloc(int(n), _kind(kind), _dtype_code(dtype), float(dt), float(dx), float(alpha),
+                                       int(tile_width), int(steps_per_cycle), ctypes.c_void_p(u.data_ptr()),
+                                       int(steps), _stream_ptr(u, stream)))
+
+
 def naive_run(plan, u, steps: int, stream=None) -> None:
     check(_lib.lib().naive_run(plan, ctypes.c_void_p(u.data_ptr()), int(steps), _stream_ptr(u, stream)))
 
@@ -488,7 +497,7 @@ class Plan:
         self.close()
 
 
-__all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "naive_run", "swept_plan_info",
+__all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "swept_run_noalloc", "naive_run", "swept_plan_info",
            "swept_plan_set_engine", "swept_plan_destroy", "swept_last_error", "swept_schedule",
            "swept_tile_geometry", "swept_autotune", "swept_autotune_lookup", "swept_autotune_forget",
            "Batch", "swept_batch_create", "swept_batch_run", "swept_batch_set_engine", "swept_batch_info",

@@ -161,3 +161,29 @@ def test_insulated_rod_shares_the_heat_tiling():
     for w in (512, 1024):
         assert P.swept_tile_geometry("heat_insulated", w) == P.swept_tile_geometry("heat", w)
         assert P.swept_schedule("heat_insulated", w, 0, 1000) == P.swept_schedule("heat", w, 0, 1000)
+
+
+def _noalloc(n=1024, kind=0, dtype=1, dt=1e-6, dx=1e-3, alpha=1.0, w=64, spc=0, u=1, steps=10):
+    return _lib.lib().swept_run_noalloc(n, kind, dtype, dt, dx, alpha, w, spc, ctypes.c_void_p(u), steps, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(kind=7), _lib.SWEPT_EINVAL),
+    (dict(dx=0.0), _lib.SWEPT_EINVAL),
+    (dict(w=96), _lib.SWEPT_EUNSUPPORTED),
+    (dict(steps=-1), _lib.SWEPT_EINVAL),
+    (dict(u=0), _lib.SWEPT_EINVAL),
+    # edge slots beyond the 32 MiB static array: 2 (2^22 / 1024) 1026 x 8 bytes
+    (dict(n=1 << 22, w=1024), _lib.SWEPT_EUNSUPPORTED),
+    (dict(n=1 << 22, w=1024, kind=1), _lib.SWEPT_EUNSUPPORTED),
+])
+def test_noalloc_rejects_before_any_device_call(kw, code):
+    # the pointer given for u is never dereferenced: every case fails first
+    assert _noalloc(**kw) == code
+    assert P.swept_last_error()
+
+
+def test_noalloc_size_limit_message():
+    assert _noalloc(n=1 << 22, w=1024) == _lib.SWEPT_EUNSUPPORTED
+    msg = P.swept_last_error()
+    assert "static workspace" in msg and str(2 * 4096 * 1026 * 8) in msg
