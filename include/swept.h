@@ -97,7 +97,14 @@ typedef struct swept_plan_s* swept_plan;
 /*
  * swept_plan_create -- build a plan for one periodic grid of n points.
  *   out             receives the plan handle (host pointer, required).
- *   n               number of grid points, >= tile width, multiple of it.
+ *   n               number of grid points: a multiple of the tile width, or,
+ *                   for tile width 512 or 1024 and n >= 32 (periodic kinds),
+ *                   any n -- then the ring is cut into tiles of uneven width
+ *                   (two halves of at most tile_width / 2 points each, all
+ *                   but one half a multiple of 4 s points; the edge passing
+ *                   of Sec. 4.2 needs no equal tiles), run on the compacted
+ *                   engine; the phase height is then at most the smallest
+ *                   half's triangle.
  *   kind, dtype     SWEPT_HEAT_FTCS / SWEPT_KS_RK2 / SWEPT_HEAT_INSULATED,
  *                   SWEPT_F32 / SWEPT_F64.
  *   dt, dx          timestep and grid spacing (finite, dx != 0).
@@ -107,7 +114,8 @@ typedef struct swept_plan_s* swept_plan;
  *                   the autotuned configuration for (kind, dtype, n) when
  *                   one is known (see swept_autotune; used only together with
  *                   steps_per_cycle = 0), else the largest power of two up to
- *                   1024 dividing n.
+ *                   1024 dividing n if it is at least 256, else the uneven
+ *                   tiling at 1024 (n >= 32).
  *   steps_per_cycle timesteps per full phase: 1..w/2 (heat), 1..w/8 (KS);
  *                   0 = the pure triangle height (w/2 heat, w/8 KS).
  * Discretisation constants are formed once on the host in double and, for
@@ -139,8 +147,8 @@ int swept_run(swept_plan p, void* u, int64_t steps, void* stream);
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  Arguments n .. steps_per_cycle are those
  * of swept_plan_create and are validated the same way, except that
- * tile_width = 0 takes the default width (the largest power of two up to 1024
- * dividing n) and never the autotuner's table; u, steps and stream are those
+ * tile_width = 0 takes the default width (as swept_plan_create without an
+ * autotuned entry) and never the autotuner's table; u, steps and stream are those
  * of swept_run, and the result is the same, bit for bit.  Nothing is
  * allocated: the edge slots live in a static array in the library's device
  * memory, 32 MiB per GPU (held by each GPU the library runs on until the
@@ -174,8 +182,9 @@ int swept_plan_info(swept_plan p, int* tile_width, int* steps_per_cycle, size_t*
  * swept_plan_set_engine -- choose the kernel that runs the phases:
  * SWEPT_ENGINE_AUTO, _LDS, _WAVE or _COMPACT.  _WAVE requires tile_width =
  * 64*P with P in {2, 4, 8, 16} for heat and {4, 8, 16} for KS; _COMPACT
- * requires P in {8, 16} for either kind; otherwise the call fails with
- * EUNSUPPORTED and the plan keeps its engine.  Every engine computes the
+ * requires P in {8, 16} for either kind; a plan of uneven tiles (tile width
+ * not dividing n) runs on _COMPACT (or AUTO) only; otherwise the call fails
+ * with EUNSUPPORTED and the plan keeps its engine.  Every engine computes the
  * same values bit for bit and leaves the same edge slots, so the choice
  * changes only the speed.  An engine whose launch would exceed the size limit
  * of swept_plan_create also fails with EUNSUPPORTED.
@@ -227,8 +236,9 @@ typedef struct {
 /*
  * swept_autotune -- time the candidate configurations for a grid of n points
  * and remember the fastest for (kind, dtype, n).  Candidates: every
- * power-of-two tile width 64..2048 that divides n, each engine that has a
- * kernel for it, and the full and half phase heights -- the per-size search
+ * power-of-two tile width 64..2048 that divides n (and 512 and 1024 with
+ * uneven tiles when they do not), each engine that has a kernel for it, and
+ * phase heights of 1, 3/4, 1/2 and 1/4 of the full triangle -- the per-size search
  * of the best launch configuration of Sec. 5, extended to the swept
  * parameters.  Each candidate runs `steps` timesteps (0 = 2048 heat / 512 KS;
  * clamped to 4096 / 1024) on a library-owned zero grid, once to warm up and
@@ -266,9 +276,8 @@ typedef struct swept_batch_s* swept_batch;
  * swept_batch_create -- plan a batch of nprob independent periodic grids of
  * uneven size, all of one kind and dtype, each advanced by `steps` timesteps
  * per swept_batch_run.
- *   n[i]                 points of grid i (host array): a multiple of 16,
- *                        32 <= n[i] <= 2^30 (each lane of a wave holds 16
- *                        points; other sizes fail with EUNSUPPORTED)
+ *   n[i]                 points of grid i (host array): any 32 <= n[i] <= 2^30
+ *                        (other sizes fail with EUNSUPPORTED)
  *   dt[i], dx[i], alpha[i]  per-grid parameters (host arrays; alpha is read
  *                        for heat only and may be NULL for KS); constants are
  *                        formed as in swept_plan_create
@@ -276,15 +285,15 @@ typedef struct swept_batch_s* swept_batch;
  * from swept_batch_info).  With the default engine (AUTO, the same as
  * RESIDENT), every grid of at most 16384 points runs whole in one workgroup
  * of 1, 4, 8 or 16 waves, 16 points per lane held in registers for all the
- * steps, halos passed between lanes and waves each sub-step: a single tile
- * whose phase is the whole run, with no edge band through HBM; these
- * workgroups run beside the persistent kernel.  Every other grid (every grid
- * with the COMPACT or WAVE engine) is run with the swept rule of swept_run:
- * wave-resident tiles
- * of at most 64 P points (P = 8 points per lane for heat with the COMPACT
- * engine, 16 otherwise) with two halves of equal or neighbouring whole-lane
- * widths (uneven tiles, flattened phases on the wider halves), zig-zag
- * tilings, edge bands through HBM (Sec. 4.2-4.3), by one persistent kernel:
+ * steps (the last lane holding the n mod 16 remaining points), halos passed
+ * between lanes and waves each sub-step: a single tile whose phase is the
+ * whole run, with no edge band through HBM; these workgroups run beside the
+ * persistent kernel.  Every other grid (every grid with the COMPACT or WAVE
+ * engine) is run with the swept rule of swept_run: wave-resident tiles of at
+ * most 64 P points (P = 8 points per lane for heat with the COMPACT engine,
+ * 16 otherwise) with two halves of uneven width (measured in points; in
+ * whole 16-point lanes for WAVE), flattened phases on the wider halves,
+ * zig-zag tilings, edge bands through HBM (Sec. 4.2-4.3), by one persistent kernel:
  * each workgroup pulls the next grid, largest first, from a device counter
  * and advances it through all of its phases.  The plan owns the edge slots,
  * the grid descriptors and the counter.  Each resident size class is one
@@ -311,7 +320,8 @@ int swept_batch_run(swept_batch b, void* u, int use_graph, void* stream);
  * rest as compacted swept tiles), SWEPT_ENGINE_COMPACT (every grid as
  * compacted swept tiles: compacted layouts, edge bands in LDS),
  * SWEPT_ENGINE_WAVE (every grid as register-engine swept tiles, every tier
- * over the whole tile) or SWEPT_ENGINE_AUTO (the default, the same as
+ * over the whole tile; every n[i] must be a multiple of 16, else
+ * EUNSUPPORTED) or SWEPT_ENGINE_AUTO (the default, the same as
  * RESIDENT: measured fastest on the 4096-grid heat and KS workloads).  All
  * give the same values bit for bit.  Changing the
  * engine rebuilds the grid descriptors and edge slots, re-sizes the

@@ -34,7 +34,7 @@ FLAGS = [
     f"-I{CSRC}",
 ]
 
-SOURCES = ["plan.hip", "naive.hip", "phase_lds.hip", "phase_wave.hip", "phase_compact.hip", "autotune.hip", "batch.hip", "adjoint.hip",
+SOURCES = ["plan.hip", "naive.hip", "phase_lds.hip", "phase_wave.hip", "phase_compact.hip", "phase_general.hip", "autotune.hip", "batch.hip", "adjoint.hip",
            "adjoint_ks.hip", "poison.hip"]
 
 

@@ -13,15 +13,18 @@
 // meet at a workgroup barrier between phases.  No workgroup ever waits for
 // another, so every wave reaches the exit when the queue runs dry.
 //
-// Tiling of one problem of n points (n a multiple of P): the ring is c = n/P
-// lane-chunks, split into 2 nt halves of floor(c/2nt) or ceil(c/2nt) lanes
-// with nt = ceil(c/64), so every half is at most 32 lanes.  Even tile j is
-// halves (2j, 2j+1), odd tile j is halves (2j+1, 2j+2 mod 2nt): the zig-zag of
-// Sec. 4.2 with uneven tiles.  The phase height is the pure-triangle height of
-// the smallest half, floor(c/2nt) P / s tiers (even for KS); larger halves
-// carry a flat top.  The per-tile algorithm is either the register engine's
-// (wave_tile.h) or the compacted one (compact_tile.h, uneven-tile form, with
-// LDS band buffers and staging rows of its own for every wave).
+// Tiling of one problem of n points, split into 2 nt halves (nt tiles per
+// tiling).  Even tile j is halves (2j, 2j+1), odd tile j is halves (2j+1,
+// 2j+2 mod 2nt): the zig-zag of Sec. 4.2 with uneven tiles.  The phase height
+// is the pure-triangle height of the smallest half (even for KS); larger
+// halves carry a flat top.  The per-tile algorithm is either
+//  - the compacted one (compact_tile.h, uneven-tile form, with LDS band
+//    buffers and staging rows of its own for every wave): any n >= 32, halves
+//    measured in points (compact::uneven_tiling: all but the last a multiple
+//    of 4 s, every one at most 32 P points); or
+//  - the register engine's (wave_tile.h), whose halves are whole lanes: n a
+//    multiple of P, c = n/P lane-chunks, halves of floor(c/2nt) or
+//    ceil(c/2nt) lanes with nt = ceil(c/64).
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -44,7 +47,7 @@ template <typename T>
 struct BatchItem {
   int64_t u_off;     // first point of this ring in the concatenated state
   int64_t slot_off;  // first value of its 2 nt edge slots
-  int32_t n;         // ring points (multiple of P)
+  int32_t n;         // ring points
   int32_t nt;        // tiles per tiling
   int32_t h;         // tiers per full phase
   int32_t pad;
@@ -76,10 +79,11 @@ batch_kernel(const BatchItem<T>* __restrict__ items, int nitems, T* u, T* slots,
     T* ring = u + pr.u_off;
     T* slotA = slots + pr.slot_off;
     T* slotB = slotA + (int64_t)pr.nt * SLEN;
-    const int c = pr.n / P;
     const int halves = 2 * pr.nt;
+    const int c = pr.n / P;  // register engine: lanes of P points
     const int hb = c / halves;
     const int hx = c % halves;
+    const compact::Uneven ut = compact::uneven_tiling(pr.n, P, S);  // compacted engine: halves in points
     const int64_t full = tiers / pr.h;
     const int rem = (int)(tiers % pr.h);
     const int64_t ne = full + (rem ? 1 : 0);  // edge sets; phases = ne + 1
@@ -90,17 +94,21 @@ batch_kernel(const BatchItem<T>* __restrict__ items, int nitems, T* u, T* slots,
       for (int j = wave; j < pr.nt; j += NW) {
         const int iL = 2 * j + parity;
         const int iR = (iL + 1) % halves;
-        wave::Tile<T> g;
-        g.origin = (int64_t)(iL * hb + min(iL, hx)) * P;
-        g.kL = hb + (iL < hx ? 1 : 0);
-        g.kR = hb + (iR < hx ? 1 : 0);
-        g.sL = parity ? slotB + (int64_t)j * SLEN : slotA + (int64_t)j * SLEN;
-        g.sR = parity ? slotA + (int64_t)((j + 1) % pr.nt) * SLEN : slotB + (int64_t)j * SLEN;
-        if constexpr (COMPACT)
-          compact::tile_phase_g<KIND, T, P>(ring, pr.n, g.origin, g.sL, g.sR, g.kL, g.kR, hv, hl, pr.k, lane,
-                                            sbm[wave], stgm[wave]);
-        else
+        T* sL = parity ? slotB + (int64_t)j * SLEN : slotA + (int64_t)j * SLEN;
+        T* sR = parity ? slotA + (int64_t)((j + 1) % pr.nt) * SLEN : slotB + (int64_t)j * SLEN;
+        if constexpr (COMPACT) {
+          compact::tile_phase_g<KIND, T, P>(ring, pr.n, compact::uneven_origin(ut, iL), sL, sR,
+                                            compact::uneven_width(ut, iL), compact::uneven_width(ut, iR), hv, hl,
+                                            pr.k, lane, sbm[wave], stgm[wave]);
+        } else {
+          wave::Tile<T> g;
+          g.origin = (int64_t)(iL * hb + min(iL, hx)) * P;
+          g.kL = hb + (iL < hx ? 1 : 0);
+          g.kR = hb + (iR < hx ? 1 : 0);
+          g.sL = sL;
+          g.sR = sR;
           wave::tile_phase<KIND, T, P, 3>(ring, pr.n, g, hv, hl, pr.k, lane);
+        }
       }
       // the next phase's tiles read slots other waves of this group wrote
       __threadfence();
@@ -122,6 +130,17 @@ batch_kernel(const BatchItem<T>* __restrict__ items, int nitems, T* u, T* slots,
 // sub-step) between waves and across the periodic seam.  Each point gets the
 // same update in the same order as in every other engine, so the results are
 // the naive run's bit for bit.
+//
+// Any n: the ring's c = ceil(n/16) lanes hold 16 points each but the last,
+// which holds M = n - 16 (c - 1) (1 .. 16).  M is a compile-time case of the
+// kernel.  At each exchange the last lane writes the ring's first two points
+// (its right halo) into its registers M and M + 1 -- for M = 15 the second goes
+// to its right halo value -- so its valid points read them in place, and the
+// lane to its left, which reads the last lane's first two registers, sees
+// point 0 where the last lane ends after one point (M = 1).  The points in its
+// registers above M + 1 are don't-care.  The ring's last two points (the left
+// halo of lane 0) come from registers M - 2 and M - 1 of the last lane, or,
+// for M = 1, from the last register of the lane before it.
 constexpr int kResQ = 16;                // points per lane
 constexpr int kResClasses = 4;
 constexpr int kResWaves[kResClasses] = {16, 8, 4, 1};  // waves per workgroup of each size class
@@ -136,58 +155,82 @@ __host__ __device__ constexpr int res_class(int64_t n) {
 constexpr int kResStreams = 3;
 constexpr int kResStreamOf[kResClasses] = {0, 1, 2, 2};
 
-template <int KIND, typename T, int NW>
-__global__ void __launch_bounds__(64 * NW)
-resident_kernel(const BatchItem<T>* __restrict__ items, T* u, int64_t steps) {
+// LDS halo exchange buffers of one resident workgroup.
+template <typename T, int NW, int D>
+struct ResLds {
+  T edF[2][NW][D];  // per wave: the first D points of its lane 0
+  T edL[2][NW][D];  // per wave: the last D points of its lane 63
+  T edC[2][D];      // the last D points of the ring
+};
+
+template <int KIND, typename T, int NW, int M>
+__device__ __forceinline__ void resident_body(const BatchItem<T>& pr, T* u, int64_t steps, ResLds<T, NW, 2>& L) {
   static_assert(Radius<KIND>::value <= 2, "one exchange holds two halo points per side");
+  static_assert(M >= 1 && M <= kResQ, "points in the last lane");
   constexpr int Q = kResQ;
   // halo depth of one exchange: two points per side, which is one KS
   // sub-step or two heat steps
   constexpr int D = 2;
-  __shared__ T edF[2][NW][D];  // per wave: the first D points of its lane 0
-  __shared__ T edL[2][NW][D];  // per wave: the last D points of its lane 63
-  __shared__ T edC[2][D];      // the last D points of the ring (lane c-1)
-  const BatchItem<T> pr = items[blockIdx.x];
   const int g = threadIdx.x;
   const int lane = g & 63;
   const int wv = g >> 6;
-  const int c = pr.n / Q;             // lanes holding points
+  const int c = (pr.n + Q - 1) / Q;   // lanes holding points
   const bool busy = wv * 64 < c;      // wave-uniform: the wave holds points
   const bool active = g < c;
+  const bool rag = g == c - 1;        // the ring's last lane (M points)
   // halos that do not come from the neighbouring lane of the same wave
   const bool first = active && lane == 0;
-  const bool last = active && (lane == 63 || g == c - 1);
+  const bool last = active && (lane == 63 || rag);
   T* ring = u + pr.u_off;
   T A[Q], B[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) A[i] = active ? ring[(int64_t)g * Q + i] : T(0);
+  for (int i = 0; i < Q; ++i) A[i] = (active && (i < M || !rag)) ? ring[(int64_t)g * Q + i] : T(0);
   int sub = 0;
   // Publish this lane's edge points, then gather the D halo points per side
-  // of src: lo[i] = point i - D, hi[i] = point Q + i.
-  auto exchange = [&](const T (&src)[Q], T (&lo)[D], T (&hi)[D]) {
+  // of src: lo[i] = point i - D, hi[i] = point Q + i.  The last lane first
+  // takes the ring's first points into its registers M, M + 1.
+  auto exchange = [&](T (&src)[Q], T (&lo)[D], T (&hi)[D]) {
     const int bf = sub & 1;
     if (busy) {
       if (active && lane == 0)
 #pragma unroll
-        for (int i = 0; i < D; ++i) edF[bf][wv][i] = src[i];
+        for (int i = 0; i < D; ++i) L.edF[bf][wv][i] = src[i];
       if (active && lane == 63)
 #pragma unroll
-        for (int i = 0; i < D; ++i) edL[bf][wv][i] = src[Q - D + i];
-      if (g == c - 1)
+        for (int i = 0; i < D; ++i) L.edL[bf][wv][i] = src[Q - D + i];
+      if (rag) {
 #pragma unroll
-        for (int i = 0; i < D; ++i) edC[bf][i] = src[Q - D + i];
+        for (int i = 0; i < D; ++i)
+          if (M - D + i >= 0) L.edC[bf][i] = src[M - D + i];
+      }
+      if constexpr (M < D) {
+        if (g == c - 2)
+#pragma unroll
+          for (int i = 0; i < D - M; ++i) L.edC[bf][i] = src[Q - (D - M) + i];
+      }
     }
     __syncthreads();
     T xl[D] = {}, xr[D] = {};
     if (first) {
 #pragma unroll
-      for (int i = 0; i < D; ++i) xl[i] = g == 0 ? edC[bf][i] : edL[bf][wv - 1][i];
+      for (int i = 0; i < D; ++i) xl[i] = g == 0 ? L.edC[bf][i] : L.edL[bf][wv - 1][i];
     }
     if (last) {
 #pragma unroll
-      for (int i = 0; i < D; ++i) xr[i] = g == c - 1 ? edF[bf][0][i] : edF[bf][wv + 1][i];
+      for (int i = 0; i < D; ++i) xr[i] = rag ? L.edF[bf][0][i] : L.edF[bf][wv + 1][i];
+    }
+    if constexpr (M < Q) {
+      src[M] = wave::pick(rag, xr[0], src[M]);
+      if constexpr (M + 1 < Q) src[M + 1] = wave::pick(rag, xr[1], src[M + 1]);
     }
     wave::halos<T, Q, D, true>(src, xl, xr, first, last, lo, hi);
+    if constexpr (M == Q - 1) hi[0] = wave::pick(rag, xr[1], hi[0]);
+    if constexpr (M == 1) {
+      // the lane before the last reads point 0 as its second right halo
+      // point (also when it ends a wave, where edF holds the unpatched value)
+      const T p0 = L.edF[bf][0][0];
+      hi[1] = wave::pick(g == c - 2, p0, hi[1]);
+    }
     ++sub;
   };
   const Consts<T> k = pr.k;
@@ -242,7 +285,34 @@ resident_kernel(const BatchItem<T>* __restrict__ items, T* u, int64_t steps) {
   }
   if (active) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) ring[(int64_t)g * Q + i] = A[i];
+    for (int i = 0; i < Q; ++i)
+      if (i < M || !rag) ring[(int64_t)g * Q + i] = A[i];
+  }
+}
+
+template <int KIND, typename T, int NW>
+__global__ void __launch_bounds__(64 * NW)
+resident_kernel(const BatchItem<T>* __restrict__ items, T* u, int64_t steps) {
+  __shared__ ResLds<T, NW, 2> L;
+  const BatchItem<T> pr = items[blockIdx.x];
+  // points in the ring's last lane (workgroup-uniform)
+  switch (pr.n - (pr.n - 1) / kResQ * kResQ) {
+    case 1: resident_body<KIND, T, NW, 1>(pr, u, steps, L); break;
+    case 2: resident_body<KIND, T, NW, 2>(pr, u, steps, L); break;
+    case 3: resident_body<KIND, T, NW, 3>(pr, u, steps, L); break;
+    case 4: resident_body<KIND, T, NW, 4>(pr, u, steps, L); break;
+    case 5: resident_body<KIND, T, NW, 5>(pr, u, steps, L); break;
+    case 6: resident_body<KIND, T, NW, 6>(pr, u, steps, L); break;
+    case 7: resident_body<KIND, T, NW, 7>(pr, u, steps, L); break;
+    case 8: resident_body<KIND, T, NW, 8>(pr, u, steps, L); break;
+    case 9: resident_body<KIND, T, NW, 9>(pr, u, steps, L); break;
+    case 10: resident_body<KIND, T, NW, 10>(pr, u, steps, L); break;
+    case 11: resident_body<KIND, T, NW, 11>(pr, u, steps, L); break;
+    case 12: resident_body<KIND, T, NW, 12>(pr, u, steps, L); break;
+    case 13: resident_body<KIND, T, NW, 13>(pr, u, steps, L); break;
+    case 14: resident_body<KIND, T, NW, 14>(pr, u, steps, L); break;
+    case 15: resident_body<KIND, T, NW, 15>(pr, u, steps, L); break;
+    default: resident_body<KIND, T, NW, 16>(pr, u, steps, L); break;
   }
 }
 
@@ -528,13 +598,22 @@ std::vector<BatchItem<T>> make_items(const swept_batch_s* b, int engine, int P, 
     if (resident(b, engine, i)) continue;
     items.emplace_back();
     BatchItem<T>& it = items.back();
-    const int c = (int)(b->n[(size_t)i] / P);
+    const int64_t n = b->n[(size_t)i];
     it.u_off = b->offsets[(size_t)i];
     it.slot_off = soff;
-    it.n = (int32_t)b->n[(size_t)i];
-    it.nt = (c + 63) / 64;
-    const int hb = c / (2 * it.nt);
-    int h = hb * P / S;
+    it.n = (int32_t)n;
+    int h;
+    if (compact_engine(engine)) {
+      // halves in points, at most 32 P each (compact::uneven_tiling)
+      const swept::compact::Uneven ut = swept::compact::uneven_tiling(n, P, S);
+      it.nt = (int32_t)ut.nt;
+      h = swept::compact::uneven_full_tiers(ut, S);
+    } else {
+      // halves of whole lanes of P points (n a multiple of P)
+      const int c = (int)(n / P);
+      it.nt = (c + 63) / 64;
+      h = c / (2 * it.nt) * P / S;
+    }
     if (b->kind == SWEPT_KS_RK2) h &= ~1;
     it.h = h;
     it.pad = 0;
@@ -649,9 +728,8 @@ int swept_batch_create(swept_batch* out, int32_t nprob, const int64_t* n, int ki
   if (!n || !dt || !dx || (kind == SWEPT_HEAT_FTCS && !alpha)) return bfail(SWEPT_EINVAL, "null host array");
   if (steps < 0) return bfail(SWEPT_EINVAL, "steps must be >= 0");
   for (int32_t i = 0; i < nprob; ++i) {
-    if (n[i] < 32 || n[i] % 16 != 0 || n[i] > (int64_t)1 << 30)
-      return bfail(SWEPT_EUNSUPPORTED, "problem " + std::to_string(i) +
-                                           ": n must be a multiple of 16, at least 32 and at most 2^30");
+    if (n[i] < 32 || n[i] > (int64_t)1 << 30)
+      return bfail(SWEPT_EUNSUPPORTED, "problem " + std::to_string(i) + ": n must be at least 32 and at most 2^30");
     if (!std::isfinite(dt[i]) || !std::isfinite(dx[i]) || dx[i] == 0.0 ||
         (kind == SWEPT_HEAT_FTCS && !std::isfinite(alpha[i])))
       return bfail(SWEPT_EINVAL, "problem " + std::to_string(i) + ": dt, dx (and alpha) must be finite, dx != 0");
@@ -710,6 +788,13 @@ int swept_batch_set_engine(swept_batch b, int engine) {
       engine != SWEPT_ENGINE_RESIDENT)
     return bfail(SWEPT_EINVAL, "unknown engine");
   if (engine == b->engine) return SWEPT_OK;
+  if (engine == SWEPT_ENGINE_WAVE) {
+    // the register engine's tile halves are whole lanes of 16 points
+    for (int32_t i = 0; i < b->nprob; ++i)
+      if (b->n[(size_t)i] % 16 != 0)
+        return bfail(SWEPT_EUNSUPPORTED, "problem " + std::to_string(i) +
+                                             ": the register engine needs n to be a multiple of 16");
+  }
   int prev = -1;
   hipError_t e = hipGetDevice(&prev);
   if (e == hipSuccess && prev != b->device) e = hipSetDevice(b->device);

@@ -113,13 +113,17 @@ __device__ __forceinline__ void v_run(T (&A)[R], T (&Q)[R], const T (&buf)[R][2]
 // values of tier t ([S t, S t + 2S), lanes b and b+1; [64 R - S(t+2),
 // 64 R - S t), lanes 63-b and 62-b), then computes tier t+1 unless
 // t == tskip (the empty top of a full triangle; never inside a FULL block).
-template <int KIND, typename T, int R, bool FULL, bool INS = false>
+// SEL: collect the left band only where colL and the right band only where
+// colR (a tile of uneven width collects its two bands in two passes).
+template <int KIND, typename T, int R, bool FULL, bool INS = false, bool SEL = false>
 __device__ __forceinline__ void l_blk(T (&A)[R], T (&Q)[R], T (&buf)[R][2], int b, int t0, int t1, int tskip,
-                                      int lane, const Consts<T>& k, wave::Ends e = wave::Ends{}) {
+                                      int lane, const Consts<T>& k, wave::Ends e = wave::Ends{}, bool colL = true,
+                                      bool colR = true) {
   constexpr int S = Radius<KIND>::value;
   constexpr int B = R / S;
-  const bool mL0 = lane == b, mL1 = lane == b + 1;
-  const bool mR0 = lane == 63 - b, mR1 = lane == 62 - b;
+  const bool cl = !SEL || colL, cr = !SEL || colR;
+  const bool mL0 = cl && lane == b, mL1 = cl && lane == b + 1;
+  const bool mR0 = cr && lane == 63 - b, mR1 = cr && lane == 62 - b;
   const T tip0[S] = {};
 #pragma unroll
   for (int j = 0; j < B; ++j) {
@@ -143,19 +147,20 @@ __device__ __forceinline__ void l_blk(T (&A)[R], T (&Q)[R], T (&buf)[R][2], int 
 
 // Lambda tiers [t0, t1) of a layout: a guarded head block when t0 is not a
 // block boundary, whole blocks, then the guarded remainder.
-template <int KIND, typename T, int R, bool INS = false>
+template <int KIND, typename T, int R, bool INS = false, bool SEL = false>
 __device__ __forceinline__ void l_run(T (&A)[R], T (&Q)[R], T (&buf)[R][2], int t0, int t1, int tskip, int lane,
-                                      const Consts<T>& k, wave::Ends e = wave::Ends{}) {
+                                      const Consts<T>& k, wave::Ends e = wave::Ends{}, bool colL = true,
+                                      bool colR = true) {
   constexpr int B = R / Radius<KIND>::value;
   if (t1 <= t0) return;
   int b = t0 / B;
   const int bl = (t1 - 1) / B;
   if (t0 % B != 0 && b < bl) {
-    l_blk<KIND, T, R, false, INS>(A, Q, buf, b, t0, t1, tskip, lane, k, e);
+    l_blk<KIND, T, R, false, INS, SEL>(A, Q, buf, b, t0, t1, tskip, lane, k, e, colL, colR);
     ++b;
   }
-  for (; b < bl; ++b) l_blk<KIND, T, R, true, INS>(A, Q, buf, b, t0, t1, -1, lane, k, e);
-  l_blk<KIND, T, R, false, INS>(A, Q, buf, bl, t0, t1, tskip, lane, k, e);
+  for (; b < bl; ++b) l_blk<KIND, T, R, true, INS, SEL>(A, Q, buf, b, t0, t1, -1, lane, k, e, colL, colR);
+  l_blk<KIND, T, R, false, INS, SEL>(A, Q, buf, bl, t0, t1, tskip, lane, k, e, colL, colR);
 }
 
 // Where a tile of an insulated rod holds the rod's ends (all false for the
@@ -404,22 +409,85 @@ __device__ __forceinline__ void tile_phase(T* u, int64_t n, int64_t origin, T* s
 }
 
 // ---------------------------------------------------------------------------
-// Tiles with uneven halves (the batched kernel): kL and kR lanes of P points
-// left and right of the seam (1 .. 32 each), w = (kL + kR) P, seam a = kL P.
-// The V layouts are centred on the seam as above; the Lambda layouts on the
-// tile middle c = w / 2, starting with the narrowest layout that holds the
-// whole base (window [c - 32R, c + 32R) covering [0, w)), whose first tier is
-// then not a block boundary.  Layout points outside the tile are don't-care:
-// their LDS loads read zero and their stores are skipped.  The row passes
-// between the V and the Lambda part through the staging row.
+// Tiles with uneven halves (the batched kernel, and single grids whose size no
+// tile width divides): wL and wR points left and right of the seam (1 .. 32 P
+// each), w = wL + wR, seam a = wL.  The V layouts are centred on the seam as
+// above, so their band positions are compile-time for any a.  The Lambda
+// triangle of tier t is [S t, w - S t).  Layout R is entered at the even tier
+// f = the smallest even tier at which the triangle fits 64 R points, with its
+// window [S f, S f + 64 R) at the triangle's left end, so its virtual tiers
+// t - f have the parity of the true tiers (the slot parity, and for KS the
+// predictor/final alternation, follow it) and its left band sits at
+// compile-time positions.  Its right band does too when the window is exactly
+// as wide as the triangle at tier f, which holds when w is a multiple of 4S.
+// Otherwise the triangle is climbed twice from the same base row: once in
+// these windows collecting the left band, once in windows ending at the
+// triangle's right end, [w - S f - 64 R, w - S f), collecting the right band;
+// each pass merges only its own side of the tile (x < w/2, x >= w/2) into the
+// band buffer.  Between the passes the base row waits in the tile's own span
+// of u, which no tile reads or writes between the up and the down phase.
+// Layout points outside the tile are don't-care: their LDS loads read zero
+// and their stores are skipped.
+
+// Tiling of a ring of n points into 2 nt halves for tiles of at most 64 P
+// points: every half but the last is `base` or `base + q` points with
+// q = 4 S (a multiple of q), the last half takes the rest (`last`, base ..
+// base + q - 1 points), so every tile but the two holding the last half has a
+// width that is a multiple of 4 S.  nt = ceil(n / (64 P - 2 q)) keeps every
+// half within 32 P points.
+struct Uneven {
+  int64_t nt;
+  int64_t base;   // width of the narrowest halves (a multiple of q)
+  int64_t extra;  // halves 0 .. extra-1 are base + q wide
+  int64_t last;   // width of half 2 nt - 1
+  int q;
+};
+
+__host__ __device__ constexpr int64_t ceil_div64(int64_t x, int64_t d) {
+  return x >= 0 ? (x + d - 1) / d : -((-x) / d);
+}
+
+__host__ __device__ inline Uneven uneven_tiling(int64_t n, int P, int S) {
+  Uneven t{};
+  t.q = 4 * S;
+  t.nt = ceil_div64(n, 64 * P - 2 * t.q);
+  const int64_t h = n / (2 * t.nt);
+  t.base = t.q * (h / t.q);
+  const int64_t r = n - 2 * t.nt * t.base;
+  t.extra = r / t.q;
+  t.last = t.base + r % t.q;
+  return t;
+}
+
+// First point (from the ring's point 0) and width of half i.
+__host__ __device__ inline int64_t uneven_origin(const Uneven& t, int64_t i) {
+  return i * t.base + t.q * (i < t.extra ? i : t.extra);
+}
+__host__ __device__ inline int uneven_width(const Uneven& t, int64_t i) {
+  return (int)(i == 2 * t.nt - 1 ? t.last : t.base + (i < t.extra ? t.q : 0));
+}
+
+// Tiers of a full phase of the tiling: the narrowest half's triangle (whole
+// KS steps).
+__host__ __device__ inline int uneven_full_tiers(const Uneven& t, int S) {
+  int h = (int)(t.base / S);
+  if (S == 2) h &= ~1;
+  return h;
+}
 
 struct GTile {
   int w;  // tile points
   int a;  // seam
-  int c;  // middle, w / 2
 };
 
 __device__ __forceinline__ bool in_tile(int x, int w) { return (unsigned)x < (unsigned)w; }
+
+// The even tier where Lambda layout R of a w-point tile starts (see above).
+template <int KIND>
+__device__ __forceinline__ int l_entry(int w, int R) {
+  const int f = (int)ceil_div64(w - 64 * R, 2 * Radius<KIND>::value);
+  return f + (f & 1);
+}
 
 template <int KIND, typename T>
 __device__ __forceinline__ T band_ld(const T* sb, int x, int q, int w) {
@@ -460,18 +528,22 @@ __device__ __forceinline__ void v_narrow_g(T* sb, T* stg, const GTile& g, int hv
 }
 
 // Lambda layouts R, R - step, .., step (those not wider than the first one,
-// r0); the row arrives in stg.
+// r0); the row arrives in stg.  `done` counts the Lambda tiers computed.
+// mode 0: both bands, windows at the triangle's left end; 1: the left band
+// only, same windows; 2: the right band only, windows at the right end.
+// Only points in [lo, hi) are merged into the band buffer.
 template <int KIND, typename T, int P, int R>
 __device__ __forceinline__ void l_narrow_g(T* sb, T* stg, const GTile& g, int r0, int hl, bool empty_top, int& done,
-                                           int lane, const Consts<T>& k) {
+                                           int lane, const Consts<T>& k, int mode, int lo, int hi) {
   if constexpr (R > 0) {
     constexpr int S = Radius<KIND>::value;
     constexpr int ST = Step<KIND>::value;
     if (R <= r0 && done < hl) {
-      const int first = (g.c - 32 * R) / S;  // tier where this layout's window starts the triangle
-      const int next = R > ST ? (g.c - 32 * (R - ST)) / S : (1 << 30);
+      const int first = l_entry<KIND>(g.w, R);  // tier where this layout's window starts
+      const int next = R > ST ? l_entry<KIND>(g.w, R - ST) : (1 << 30);
       const int tend = hl < next ? hl : next;
-      const int xl = g.c - 32 * R + lane * R;
+      const int base = mode == 2 ? g.w - S * first - 64 * R : S * first;
+      const int xl = base + lane * R;
       T A[R], Q[R], buf[R][2];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -482,7 +554,8 @@ __device__ __forceinline__ void l_narrow_g(T* sb, T* stg, const GTile& g, int r0
         buf[r][1] = R == r0 ? T(0) : band_ld<KIND>(sb, x, 1, g.w);
       }
       const int tskip = empty_top ? hl - 1 - first : -1;
-      l_run<KIND, T, R>(A, Q, buf, done - first, tend - first, tskip, lane, k);
+      l_run<KIND, T, R, false, true>(A, Q, buf, done - first, tend - first, tskip, lane, k, wave::Ends{}, mode != 2,
+                                     mode != 1);
       done = tend;
       if (done >= hl && !empty_top) {
 #pragma unroll
@@ -501,30 +574,33 @@ __device__ __forceinline__ void l_narrow_g(T* sb, T* stg, const GTile& g, int r0
       for (int r = 0; r < R; ++r) {
         const int x = xl + r;
         if (in_tile(x, g.w)) {
-          sb[pad(2 * (x + S))] = buf[r][0];
-          sb[pad(2 * (x + S) + 1)] = buf[r][1];
+          if (x >= lo && x < hi) {
+            sb[pad(2 * (x + S))] = buf[r][0];
+            sb[pad(2 * (x + S) + 1)] = buf[r][1];
+          }
           if (done < hl) stg[pad(x)] = A[r];
         }
       }
       wave_sync();
     }
-    l_narrow_g<KIND, T, P, R - ST>(sb, stg, g, r0, hl, empty_top, done, lane, k);
+    l_narrow_g<KIND, T, P, R - ST>(sb, stg, g, r0, hl, empty_top, done, lane, k, mode, lo, hi);
   }
 }
 
 // One phase of one uneven tile: hv V tiers (0: read the row from u), then hl
-// Lambda tiers (0: write the row to u).  sL/sR are its edge slots (layout as
-// in wave_tile.h); sb and stg this wave's LDS band buffer and staging row.
+// Lambda tiers (0: write the row to u).  The tile is wL + wR points from
+// `origin` (ring index, wrapped mod n), seam at wL; sL/sR are its edge slots
+// (layout as in wave_tile.h, positions in points); sb and stg this wave's LDS
+// band buffer and staging row.  hv and hl must not exceed min(wL, wR) / S.
 template <int KIND, typename T, int P>
-__device__ __forceinline__ void tile_phase_g(T* u, int64_t n, int64_t origin, T* sL, T* sR, int kL, int kR, int hv,
+__device__ __forceinline__ void tile_phase_g(T* u, int64_t n, int64_t origin, T* sL, T* sR, int wL, int wR, int hv,
                                              int hl, const Consts<T>& k, int lane, T* sb, T* stg) {
   constexpr int S = Radius<KIND>::value;
   constexpr int ST = Step<KIND>::value;
   constexpr int NV = (2 * (32 * P + S) + 63) / 64;  // copy iterations per slot side
   GTile g;
-  g.w = (kL + kR) * P;
-  g.a = kL * P;
-  g.c = g.w / 2;
+  g.w = wL + wR;
+  g.a = wL;
   const int nL = 2 * (g.a + S), nR = 2 * (g.w - g.a + S);  // slot values read or written per side
 
   if (hv == 0) {
@@ -603,11 +679,43 @@ __device__ __forceinline__ void tile_phase_g(T* u, int64_t n, int64_t origin, T*
       if (in_tile(xl + r, g.w)) stg[pad(xl + r)] = A[r];
     wave_sync();
   }
-  // narrowest layout whose window holds the whole base: 32 r0 >= c
-  const int r0 = ((g.c + 32 * ST - 1) / (32 * ST)) * ST;
+  // narrowest layout whose window holds the whole base: 64 r0 >= w
+  const int r0 = (int)ceil_div64(g.w, 64 * ST) * ST;
   const bool empty_top = 2 * S * hl >= g.w;
-  int done = 0;
-  l_narrow_g<KIND, T, P, P>(sb, stg, g, r0, hl, empty_top, done, lane, k);
+  if (g.w % (4 * S) == 0) {
+    int done = 0;
+    l_narrow_g<KIND, T, P, P>(sb, stg, g, r0, hl, empty_top, done, lane, k, 0, 0, g.w);
+  } else {
+    // two passes from the same base row, parked in the tile's span of u
+    const int split = g.w / 2;
+#pragma unroll
+    for (int it = 0; it < P; ++it) {
+      const int x = it * 64 + lane;
+      if (x < g.w) {
+        int64_t g2 = origin + x;
+        if (g2 >= n) g2 -= n;
+        u[g2] = stg[pad(x)];
+      }
+    }
+    int done = 0;
+    l_narrow_g<KIND, T, P, P>(sb, stg, g, r0, hl, empty_top, done, lane, k, 1, 0, split);
+    T row[P];
+#pragma unroll
+    for (int it = 0; it < P; ++it) {
+      const int x = it * 64 + lane;
+      int64_t g2 = origin + x;
+      if (g2 >= n) g2 -= n;
+      row[it] = x < g.w ? u[g2] : T(0);
+    }
+#pragma unroll
+    for (int it = 0; it < P; ++it) {
+      const int x = it * 64 + lane;
+      if (x < g.w) stg[pad(x)] = row[it];
+    }
+    wave_sync();
+    done = 0;
+    l_narrow_g<KIND, T, P, P>(sb, stg, g, r0, hl, empty_top, done, lane, k, 2, split, g.w);
+  }
   // outgoing slots: producer left side p = x (x < a + S), right side
   // p = x - a + S (x >= a - S)
   {

@@ -26,8 +26,8 @@ struct PhaseArgs {
   void* u;       // device grid, n values
   void* slots;   // device edge slots: slot A[j] at j, slot B[j] at nt + j
   int64_t n;
-  int w;         // tile width
-  int64_t nt;    // tiles = n / w
+  int w;         // tile width (the widest tile of an uneven tiling)
+  int64_t nt;    // tiles: n / w, or those of the uneven tiling
   int parity;    // 0: tiles start at j*w; 1: at j*w + w/2
   int hv;        // V height in tiers (0 = load full row)
   int hl;        // Lambda height in tiers (0 = store full row)
@@ -59,6 +59,15 @@ template <int KIND, typename T>
 hipError_t launch_phase_compact(const PhaseArgs& a, const Consts<T>& k, hipStream_t st);
 // Whether the compacted wave engine has a kernel for this kind and width.
 bool compact_engine_supports(int kind, int w);
+// Uneven tiling of a single grid whose size the tile width w (512 or 1024)
+// does not divide: tiles of two halves of at most w / 2 points each, on the
+// compacted engine (phase_general.hip).
+template <int KIND, typename T>
+hipError_t launch_phase_general(const PhaseArgs& a, const Consts<T>& k, hipStream_t st);
+bool general_engine_supports(int w);
+int64_t general_tiles(int kind, int64_t n, int w);
+// Tiers of a full phase of the uneven tiling: the smallest half's triangle.
+int general_full_tiers(int kind, int64_t n, int w);
 // Heat on a rod with insulated ends (compacted engine; widths as for heat).
 template <typename T>
 hipError_t launch_phase_compact_insulated(const PhaseArgs& a, const Consts<T>& k, hipStream_t st);

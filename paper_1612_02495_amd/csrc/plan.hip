@@ -53,6 +53,7 @@ bool valid_kind(int kind) {
 int stencil_of(int kind) { return kind == SWEPT_KS_RK2 ? swept::kKS : swept::kHeat; }
 
 constexpr int kMinTile = 4;
+constexpr int kMinGeneral = 32;  // smallest grid of the uneven tiling
 constexpr int kMaxTile = 4096;
 
 // Tile width rules: w = 2s * (tiers of a full triangle); KS phases must end
@@ -108,6 +109,7 @@ struct swept_plan_s {
   int h = 0;       // tiers per full phase
   int64_t nt = 0;  // tiles
   int engine = SWEPT_ENGINE_AUTO;
+  bool general = false;  // uneven tiling: w does not divide n (compacted engine only)
   bool lds_fits = true;  // the LDS engine's tile fits the device's LDS
   int device = 0;
   void* slots = nullptr;
@@ -169,6 +171,9 @@ hipError_t launch_phase(const swept_plan_s* p, const PhaseArgs& a, const Consts<
 
 template <typename T>
 hipError_t dispatch_phase(const swept_plan_s* p, const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
+  if (p->general)
+    return p->kind == SWEPT_KS_RK2 ? swept::launch_phase_general<swept::kKS, T>(a, k, st)
+                                   : swept::launch_phase_general<swept::kHeat, T>(a, k, st);
   if (p->kind == SWEPT_HEAT_INSULATED) return swept::launch_phase_compact_insulated<T>(a, k, st);
   if (p->kind == SWEPT_HEAT_FTCS) return launch_phase<swept::kHeat, T>(p, a, k, st);
   return launch_phase<swept::kKS, T>(p, a, k, st);
@@ -228,28 +233,46 @@ int plan_setup(swept_plan_s* p, int64_t n, int kind, int dtype, double dt, doubl
   int w = tile_width;
   const char* why = "";
   int tuned_engine = SWEPT_ENGINE_AUTO;
+  // The uneven tiling (tile widths 512 and 1024, any n >= 32 of a periodic
+  // kind) takes the grids that the width does not divide.
+  auto uneven_ok = [&](int width) {
+    return kind != SWEPT_HEAT_INSULATED && n >= kMinGeneral && swept::general_engine_supports(width) &&
+           n % width != 0;
+  };
+  auto full_of = [&](int width) {
+    return uneven_ok(width) ? swept::general_full_tiers(stencil_of(kind), n, width) : full_tiers(kind, width);
+  };
   if (w == 0) {
     // tuned configuration for this (kind, dtype, n) if the autotuner has one
     swept::TuneEntry te;
     if (use_tuned && steps_per_cycle == 0 && swept::tune_lookup(kind, dtype, n, &te) &&
-        tile_ok(kind, te.tile_width, &why) && n % te.tile_width == 0 && te.steps_per_cycle >= 0 &&
-        te.steps_per_cycle * tiers_per_step(kind) <= full_tiers(kind, te.tile_width) &&
-        engine_supports(te.engine, kind, te.tile_width)) {
+        tile_ok(kind, te.tile_width, &why) && (n % te.tile_width == 0 || uneven_ok(te.tile_width)) &&
+        te.steps_per_cycle >= 0 && te.steps_per_cycle * tiers_per_step(kind) <= full_of(te.tile_width) &&
+        engine_supports(te.engine, kind, te.tile_width) &&
+        (n % te.tile_width == 0 || te.engine == SWEPT_ENGINE_COMPACT || te.engine == SWEPT_ENGINE_AUTO)) {
       w = te.tile_width;
       steps_per_cycle = te.steps_per_cycle;
       tuned_engine = te.engine;
     } else {
       w = choose_tile(kind, n);
+      // widths below 256 leave most of each tile's work in its edges: the
+      // uneven tiling at 1024 is used instead when it applies
+      if (w < 256 && uneven_ok(1024)) w = 1024;
     }
     if (w == 0) return fail(SWEPT_EUNSUPPORTED, "no supported tile width divides n");
   } else if (!tile_ok(kind, w, &why)) {
     return fail(SWEPT_EINVAL, why);
   }
-  if (n % w != 0 || n < w) return fail(SWEPT_EUNSUPPORTED, "n must be a positive multiple of tile_width");
+  const bool general = n % w != 0 || n < w;
+  if (general && !uneven_ok(w))
+    return fail(SWEPT_EUNSUPPORTED,
+                "n must be a positive multiple of tile_width, or tile_width 512 or 1024 with n >= 32 (uneven tiles; "
+                "not for the insulated rod)");
   if (kind == SWEPT_HEAT_INSULATED && !engine_supports(SWEPT_ENGINE_COMPACT, kind, w))
     return fail(SWEPT_EUNSUPPORTED, "the insulated rod runs on the compacted engine: tile_width 512 or 1024");
-  const int hfull = full_tiers(kind, w);
+  const int hfull = full_of(w);
   const int tps = tiers_per_step(kind);
+  if (hfull < tps) return fail(SWEPT_EUNSUPPORTED, "n too small for one timestep per phase");
   if (steps_per_cycle < 0 || steps_per_cycle * tps > hfull)
     return fail(SWEPT_EINVAL, "steps_per_cycle exceeds the triangle height of this tile width");
 
@@ -260,7 +283,8 @@ int plan_setup(swept_plan_s* p, int64_t n, int kind, int dtype, double dt, doubl
   p->s = radius_of(kind);
   p->w = w;
   p->h = steps_per_cycle ? steps_per_cycle * tps : hfull;
-  p->nt = n / w;
+  p->general = general;
+  p->nt = general ? swept::general_tiles(stencil_of(kind), n, w) : n / w;
   // Discretisation constants in double, rounded once for float (Sec. 4.1, Sec. 5).
   const double fo = (alpha * dt) / (dx * dx);
   p->kd.fo = fo;
@@ -295,10 +319,10 @@ int plan_setup(swept_plan_s* p, int64_t n, int kind, int dtype, double dt, doubl
   else
     lds = dtype == SWEPT_F64 ? swept::phase_lds_bytes<swept::kKS, double>(w)
                              : swept::phase_lds_bytes<swept::kKS, float>(w);
-  if (lds > (size_t)max_lds && !swept::wave_engine_supports(stencil_of(kind), w))
+  if (!general && lds > (size_t)max_lds && !swept::wave_engine_supports(stencil_of(kind), w))
     return fail(SWEPT_EUNSUPPORTED, "tile too wide for the LDS of this device");
-  p->engine = tuned_engine;
-  p->lds_fits = lds <= (size_t)max_lds;
+  p->engine = general ? SWEPT_ENGINE_COMPACT : tuned_engine;
+  p->lds_fits = !general && lds <= (size_t)max_lds;
   // a tuned LDS choice that this device's LDS cannot hold falls back to AUTO
   // (a register engine: the width check above guarantees one exists)
   if (!p->lds_fits && p->engine == SWEPT_ENGINE_LDS) p->engine = SWEPT_ENGINE_AUTO;
@@ -419,6 +443,8 @@ int swept_plan_set_engine(swept_plan p, int engine) {
   if (engine != SWEPT_ENGINE_AUTO && engine != SWEPT_ENGINE_LDS && engine != SWEPT_ENGINE_WAVE &&
       engine != SWEPT_ENGINE_COMPACT)
     return fail(SWEPT_EINVAL, "unknown engine");
+  if (p->general && engine != SWEPT_ENGINE_AUTO && engine != SWEPT_ENGINE_COMPACT)
+    return fail(SWEPT_EUNSUPPORTED, "tiles of uneven width (tile_width does not divide n) run on the compacted engine");
   if (!engine_supports(engine, p->kind, p->w))
     return fail(SWEPT_EUNSUPPORTED, engine == SWEPT_ENGINE_WAVE      ? "no wave-resident kernel for this kind and tile width"
                                     : engine == SWEPT_ENGINE_COMPACT ? "no compacted kernel for this kind and tile width"
@@ -527,18 +553,25 @@ int swept_autotune(int64_t n, int kind, int dtype, double dt, double dx, double 
   std::vector<Cand> cands;
   const char* why = "";
   for (int w = 64; w <= 2048; w <<= 1) {
-    if (n % w != 0 || n < w || !tile_ok(kind, w, &why)) continue;
-    const int full_steps = full_tiers(kind, w) / tps;
-    const int spcs[2] = {full_steps, full_steps / 2};
+    if (!tile_ok(kind, w, &why)) continue;
+    // widths that divide n, and the uneven tiling at 512 and 1024 otherwise
+    const bool even = n % w == 0 && n >= w;
+    const bool uneven = !even && kind != SWEPT_HEAT_INSULATED && n >= kMinGeneral && swept::general_engine_supports(w);
+    if (!even && !uneven) continue;
+    const int full_steps =
+        (uneven ? swept::general_full_tiers(stencil_of(kind), n, w) : full_tiers(kind, w)) / tps;
+    // phase heights: the full triangle, 3/4, 1/2 and 1/4 of it
+    const int spcs[4] = {full_steps, full_steps * 3 / 4, full_steps / 2, full_steps / 4};
     for (int eng : {SWEPT_ENGINE_COMPACT, SWEPT_ENGINE_WAVE, SWEPT_ENGINE_LDS}) {
-      if (!engine_supports(eng, kind, w)) continue;
-      for (int si = 0; si < 2; ++si) {
-        if (spcs[si] < 1 || (si == 1 && spcs[1] == spcs[0])) continue;
-        cands.push_back({w, spcs[si], eng});
+      if (!engine_supports(eng, kind, w) || (uneven && eng != SWEPT_ENGINE_COMPACT)) continue;
+      for (int si = 0; si < 4; ++si) {
+        bool dup = spcs[si] < 1;
+        for (int sj = 0; sj < si; ++sj) dup = dup || spcs[sj] == spcs[si];
+        if (!dup) cands.push_back({w, spcs[si], eng});
       }
     }
   }
-  if (cands.empty()) return fail(SWEPT_EUNSUPPORTED, "no tile width divides n");
+  if (cands.empty()) return fail(SWEPT_EUNSUPPORTED, "no tile width fits n");
 
   const size_t es = elem_size(dtype);
   void* u = nullptr;

@@ -114,13 +114,10 @@ def ks(n: int = 2 ** 16, seed: int = 2, steps: int = 20000) -> Problem:
     return Problem("ks", n, dt, dx, 0.0, steps, u0)
 
 
-def batch_sizes(rng: np.random.Generator, nprob: int, nmin_log2: float = 8.0, nmax_log2: float = 16.0,
-                quantum: int = 16) -> np.ndarray:
-    """N_p = quantum * round(2^U(nmin, nmax) / quantum): log-uniform sizes on the
-    lattice of whole register lanes (16 points per lane)."""
+def batch_sizes(rng: np.random.Generator, nprob: int, nmin_log2: float = 8.0, nmax_log2: float = 16.0) -> np.ndarray:
+    """N_p = round(2^U(nmin, nmax)): log-uniform integer grid sizes."""
     raw = 2.0 ** rng.uniform(nmin_log2, nmax_log2, size=nprob)
-    q = np.rint(raw / quantum).astype(np.int64) * quantum
-    return np.clip(q, int(2 ** nmin_log2), int(2 ** nmax_log2))
+    return np.rint(raw).astype(np.int64)
 
 
 def heat_batch(nprob: int = 4096, seed: int = 3, steps: int = 5000, nmin_log2: float = 8.0,

@@ -70,7 +70,9 @@ def _create(n=1024, kind=0, dtype=1, dt=1e-6, dx=1e-3, alpha=1.0, w=64, spc=0):
     (dict(w=3), _lib.SWEPT_EINVAL),             # heat: below minimum / odd
     (dict(w=8192), _lib.SWEPT_EINVAL),
     (dict(w=96), _lib.SWEPT_EUNSUPPORTED),      # 1024 % 96 != 0
-    (dict(n=1023, w=0), _lib.SWEPT_EUNSUPPORTED),  # odd n: no tile width
+    (dict(n=31, w=0), _lib.SWEPT_EUNSUPPORTED),    # odd n below the uneven tiling: no tile width
+    (dict(n=1023, w=256), _lib.SWEPT_EUNSUPPORTED),  # uneven tiles need width 512 or 1024
+    (dict(n=1023, w=512, kind=2), _lib.SWEPT_EUNSUPPORTED),  # not for the insulated rod
     (dict(spc=33), _lib.SWEPT_EINVAL),          # heat w=64: at most 32 steps per phase
     (dict(kind=1, w=64, spc=9), _lib.SWEPT_EINVAL),  # KS w=64: at most 8 steps per phase
     (dict(kind=3), _lib.SWEPT_EINVAL),

@@ -23,8 +23,9 @@ def _create(n, kind=0, dtype=1, steps=10, dt=None, dx=None, alpha=None):
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(n=[256, 250]), _lib.SWEPT_EUNSUPPORTED),   # not a multiple of 16
-    (dict(n=[16]), _lib.SWEPT_EUNSUPPORTED),          # below 32
+    (dict(n=[256, 31]), _lib.SWEPT_EUNSUPPORTED),    # below 32
+    (dict(n=[16]), _lib.SWEPT_EUNSUPPORTED),
+    (dict(n=[(1 << 30) + 1]), _lib.SWEPT_EUNSUPPORTED),  # above 2^30
     (dict(n=[256], kind=4), _lib.SWEPT_EINVAL),
     (dict(n=[256], dtype=9), _lib.SWEPT_EINVAL),
     (dict(n=[256], steps=-1), _lib.SWEPT_EINVAL),
@@ -46,10 +47,13 @@ def test_batch_null_handles():
     assert lib.swept_batch_create(ctypes.byref(h), 0, None, 0, 1, None, None, None, 1) == _lib.SWEPT_EINVAL
 
 
-def test_batch_sizes_lattice():
+def test_batch_sizes_log_uniform_integers():
     probs = inputs.heat_batch(nprob=4096)
     n = np.array([p.n for p in probs])
-    assert (n % 16 == 0).all() and n.min() >= 256 and n.max() <= 65536
+    assert n.min() >= 256 and n.max() <= 65536
+    # round(2^U(8,16)): integers of every residue, odd ones included
+    assert 0.45 < np.mean(n % 2 == 1) < 0.55
+    assert len(set((n % 16).tolist())) == 16
     # log-uniform: about a quarter of the sizes in each of [2^8,2^10), ..., [2^14,2^16]
     frac = np.histogram(np.log2(n), bins=[8, 10, 12, 14, 16.01])[0] / n.size
     assert np.all(np.abs(frac - 0.25) < 0.03)

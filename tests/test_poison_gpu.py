@@ -34,6 +34,14 @@ CASES = [
     ("ks", 256, 64, 8, 61, "lds"),
     ("heat_insulated", 2048, 1024, 0, 1100, "compact"),
     ("heat_insulated", 1536, 512, 100, 333, "compact"),
+    # tiles of uneven width (no tile width divides n): the tiles holding the
+    # ring's last half climb their triangle twice, one band per pass
+    ("heat", 3001, 1024, 0, 2100, "compact"),
+    ("heat", 1025, 512, 37, 700, "compact"),
+    ("heat", 99, 1024, 0, 170, "compact"),
+    ("ks", 3001, 1024, 0, 300, "compact"),
+    ("ks", 1001, 512, 5, 170, "compact"),
+    ("ks", 77, 1024, 0, 60, "compact"),
 ]
 
 
@@ -84,6 +92,37 @@ def test_poisoned_batch_equals_naive(poison, kind, engine):
         got = part.cpu().numpy()
         assert np.all(np.isfinite(got)), f"grid {i}: a phase read an unwritten slot entry"
         plan = Plan(int(sizes[i]), kind, torch.float64, dt[i], dx[i], alpha[i], tile_width=16)
+        v = torch.tensor(u0[i], device="cuda")
+        plan.naive(v, steps)
+        torch.cuda.synchronize()
+        assert np.array_equal(got, v.cpu().numpy()), f"grid {i} (n={sizes[i]})"
+
+
+@pytest.mark.parametrize("engine", ["auto", "compact"])
+@pytest.mark.parametrize("kind", ["heat", "ks"])
+def test_poisoned_batch_any_sizes(poison, kind, engine):
+    # sizes off the 16-point lane lattice: ragged last lanes of the whole-grid
+    # kernels, uneven swept tiles of every width residue
+    sizes = np.array([33, 47, 263, 1025, 2049, 5003, 16385, 20001, 30011], dtype=np.int64)
+    rng = np.random.default_rng(19)
+    steps = 83
+    if kind == "heat":
+        dx = 1.0 / sizes
+        dt = rng.uniform(0.05, 0.45, size=sizes.size) * dx * dx
+        alpha = np.ones(sizes.size)
+    else:
+        dx = np.full(sizes.size, 0.5)
+        dt = np.full(sizes.size, 0.005)
+        alpha = np.zeros(sizes.size)
+    u0 = [rng.standard_normal(int(m)) for m in sizes]
+    b = Batch(sizes, kind, torch.float64, dt, dx, alpha, steps).set_engine(engine)
+    u = torch.tensor(np.concatenate(u0), device="cuda")
+    b.run(u)
+    torch.cuda.synchronize()
+    for i, part in enumerate(b.split(u)):
+        got = part.cpu().numpy()
+        assert np.all(np.isfinite(got)), f"grid {i}: a phase read an unwritten slot entry"
+        plan = Plan(int(sizes[i]), kind, torch.float64, dt[i], dx[i], alpha[i])
         v = torch.tensor(u0[i], device="cuda")
         plan.naive(v, steps)
         torch.cuda.synchronize()
