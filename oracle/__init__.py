@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-fopenmp"]
 
 
 def build(force: bool = True) -> str:
@@ -53,10 +53,14 @@ def _load():
         lib.oracle_ks_f64.argtypes = [pd, i64, dbl, dbl, i64]
         lib.oracle_ks_f32.argtypes = [pf, i64, dbl, dbl, i64]
         lib.oracle_heat_adjoint_f64.argtypes = [pd, pd, i64, dbl, dbl, dbl, i64, i64, pd, pd, pd]
+        pi = ctypes.POINTER(ctypes.c_int)
+        lib.oracle_heat_f64_mt.argtypes = [pd, i64, dbl, dbl, dbl, i64, ctypes.c_int, pi]
+        lib.oracle_ks_f64_mt.argtypes = [pd, i64, dbl, dbl, i64, ctypes.c_int, pi]
         lib.oracle_ks_adjoint_f64.argtypes = [pd, pd, i64, dbl, dbl, i64, i64, pd, pd]
         for f in (lib.oracle_heat_f64, lib.oracle_heat_f32, lib.oracle_heat_insulated_f64,
                   lib.oracle_heat_insulated_f32, lib.oracle_ks_f64, lib.oracle_ks_f32,
-                  lib.oracle_heat_adjoint_f64, lib.oracle_ks_adjoint_f64):
+                  lib.oracle_heat_adjoint_f64, lib.oracle_ks_adjoint_f64, lib.oracle_heat_f64_mt,
+                  lib.oracle_ks_f64_mt):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -105,6 +109,28 @@ def ks(u0, dt: float, dx: float, steps: int, dtype=np.float64) -> np.ndarray:
     f = lib.oracle_ks_f64 if a.dtype == np.float64 else lib.oracle_ks_f32
     _check(f(_ptr(a), a.size, float(dt), float(dx), int(steps)), "oracle_ks")
     return a
+
+
+def heat_mt(u0, alpha: float, dt: float, dx: float, steps: int, threads: int = 0):
+    """heat() in FP64 with each step's points split over host threads (OpenMP);
+    the same bits as heat().  Returns (array, threads used)."""
+    lib = _load()
+    a = _arr(u0, np.float64)
+    used = ctypes.c_int(0)
+    _check(lib.oracle_heat_f64_mt(_ptr(a), a.size, float(alpha), float(dt), float(dx), int(steps), int(threads),
+                                  ctypes.byref(used)), "oracle_heat_f64_mt")
+    return a, used.value
+
+
+def ks_mt(u0, dt: float, dx: float, steps: int, threads: int = 0):
+    """ks() in FP64 with each sub-step's points split over host threads
+    (OpenMP); the same bits as ks().  Returns (array, threads used)."""
+    lib = _load()
+    a = _arr(u0, np.float64)
+    used = ctypes.c_int(0)
+    _check(lib.oracle_ks_f64_mt(_ptr(a), a.size, float(dt), float(dx), int(steps), int(threads),
+                                ctypes.byref(used)), "oracle_ks_f64_mt")
+    return a, used.value
 
 
 def heat_adjoint(u0, y, alpha: float, dt: float, dx: float, steps: int, ckpt: int = 0):

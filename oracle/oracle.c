@@ -113,6 +113,43 @@ int oracle_heat_f32(float* u, int64_t n, double alpha, double dt, double dx, int
     return ORACLE_OK;
 }
 
+/* --------------------------------------------- all host cores (OpenMP) -- */
+/*
+ * The same timesteppers with the loop over grid points of each step split
+ * over host threads (OpenMP, static schedule).  Every point is updated from
+ * the previous step's values by the same expression as above, and no value
+ * is summed across points, so the result is bit for bit that of the
+ * single-thread entry points for any thread count.  For the CPU-baseline
+ * timing on all host cores.  nthreads <= 0 takes the OpenMP default
+ * (OMP_NUM_THREADS, else the host's cores); *used receives the count.
+ */
+#include <omp.h>
+
+int oracle_heat_f64_mt(double* u, int64_t n, double alpha, double dt, double dx, int64_t steps, int nthreads,
+                       int* used) {
+    if (!u || n < 1 || steps < 0) return ORACLE_EINVAL;
+    double fo = (alpha * dt) / (dx * dx);
+    double c = 1.0 - 2.0 * fo;
+    double* v = (double*)malloc((size_t)n * sizeof(double));
+    if (!v) return ORACLE_ENOMEM;
+    int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+    if (used) *used = nt;
+    double* cur = u;
+    double* nxt = v;
+    for (int64_t m = 0; m < steps; ++m) {
+#pragma omp parallel for num_threads(nt) schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double left = cur[wrap(i - 1, n)];
+            double right = cur[wrap(i + 1, n)];
+            nxt[i] = fo * (right + left) + c * cur[i];
+        }
+        double* t = cur; cur = nxt; nxt = t;
+    }
+    if (cur != u) memcpy(u, cur, (size_t)n * sizeof(double));
+    free(v);
+    return ORACLE_OK;
+}
+
 /* ----------------------------------------------- heat, insulated rod -- */
 /*
  * The rod with insulated ends of Sec. 4.1 (Appendix, "insulated boundary
@@ -234,6 +271,26 @@ int oracle_ks_f32(float* u, int64_t n, double dt, double dx, int64_t steps) {
     for (int64_t m = 0; m < steps; ++m) {
         for (int64_t i = 0; i < n; ++i) up[i] = u[i] + fdth * ks_rhs_f32(u, n, i, i4dx, idx2, idx4);
         for (int64_t i = 0; i < n; ++i) u[i] = u[i] + fdt * ks_rhs_f32(up, n, i, i4dx, idx2, idx4);
+    }
+    free(up);
+    return ORACLE_OK;
+}
+
+int oracle_ks_f64_mt(double* u, int64_t n, double dt, double dx, int64_t steps, int nthreads, int* used) {
+    if (!u || n < 1 || steps < 0) return ORACLE_EINVAL;
+    ks_consts k = ks_make(dt, dx);
+    double* up = (double*)malloc((size_t)n * sizeof(double));
+    if (!up) return ORACLE_ENOMEM;
+    int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+    if (used) *used = nt;
+    for (int64_t m = 0; m < steps; ++m) {
+#pragma omp parallel num_threads(nt)
+        {
+#pragma omp for schedule(static)
+            for (int64_t i = 0; i < n; ++i) up[i] = u[i] + k.dth * ks_rhs_f64(u, n, i, &k);
+#pragma omp for schedule(static)
+            for (int64_t i = 0; i < n; ++i) u[i] = u[i] + k.dt * ks_rhs_f64(up, n, i, &k);
+        }
     }
     free(up);
     return ORACLE_OK;

@@ -1,7 +1,9 @@
 """Host-side checks of bench.py: it measures one GPU and refuses more, its
-ALU peak is the chip's FP64 vector rate without FMA, the traffic figure is
+roofline fraction is taken against MI355X's published vector peak for the
+dtype (with the add/mul issue rate as a second figure), the traffic figure is
 read from the committed counter summary only while the kernel sources match
-it, and the flop counts per update are the stencils' operation counts."""
+it, the CPU baseline reports its thread counts and host, and the flop counts
+per update are the stencils' operation counts."""
 import hashlib
 import os
 import subprocess
@@ -59,3 +61,30 @@ def test_traffic_read_only_for_matching_sources(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(fake_root))
     assert bench._traffic_from_profile(wl, 1024, "compact") is None
     assert hashlib.sha256(real).hexdigest()  # the real tree is untouched
+
+
+def test_roofline_uses_the_published_peak_and_the_issue_rate():
+    r = bench.roofline("k", flops=4.0e9, t_launch=1e-4, dtype="f64")
+    assert r["achieved"] == pytest.approx(40.0)
+    assert r["peak"] == 78.6 and r["frac"] == pytest.approx(40.0 / 78.6)
+    assert r["issue_peak"] == pytest.approx(39.3216) and r["frac_of_issue_peak"] == pytest.approx(40.0 / 39.3216)
+    assert r["unit"] == "TFLOP/s" and r["bound"] == "alu" and r["launch_ms"] == pytest.approx(0.1)
+    assert bench.roofline("k", 1.0, 1.0, "f32")["peak"] == 157.3
+
+
+def test_cpu_legs_report_threads_and_host():
+    out = bench.cpu_legs((lambda: None, 100, "one"), (lambda: 7, 800, "all"))
+    assert out["kind"] == "oracle" and out["cores"] == 7 and out["single_thread"]["cores"] == 1
+    assert "7 threads" in out["sample"]
+    host = out["host"]
+    assert set(host) >= {"cpu_model", "nproc", "affinity_cpus", "omp_num_threads"}
+    single_only = bench.cpu_legs((lambda: None, 100, "one"))
+    assert single_only["cores"] == 1 and single_only["value"] == single_only["single_thread"]["value"]
+
+
+def test_default_run_nests_the_rest_of_the_metric():
+    assert bench.NESTED == ["ks", "batch", "batch_ks", "adjoint", "ks_adjoint"]
+    rec = {"value": 1.0, "unit": "u", "ms_per_step": 2.0, "roofline": {}, "cpu_baseline": {}, "metric": "m",
+           "config": {"workload": "w", "autotune": [1, 2]}}
+    nr = bench.nested_record(rec)
+    assert "metric" not in nr and "autotune" not in nr["config"] and nr["ms_per_step"] == 2.0

@@ -292,3 +292,18 @@ def test_adjoint_central_differences():
         d /= np.linalg.norm(d)
         fdu = (jval(u0 + h * d, alpha) - jval(u0 - h * d, alpha)) / (2 * h)
         assert abs(fdu - np.dot(g, d)) <= 1e-6 * max(abs(np.dot(g, d)), 1e-3)
+
+
+@pytest.mark.parametrize("threads", [1, 2, 3, 8])
+@pytest.mark.parametrize("n", [5, 97, 4096, 30011])
+def test_all_cores_oracle_gives_the_single_thread_bits(n, threads):
+    # the OpenMP leg used for the CPU baseline on all host cores splits each
+    # step's points over threads; every point's update is unchanged, so the
+    # result is the single-thread oracle's bit for bit
+    u = np.random.default_rng(n).standard_normal(n)
+    a = oracle.heat(u, 1.0, 0.2 / n / n, 1.0 / n, 37)
+    b, used = oracle.heat_mt(u, 1.0, 0.2 / n / n, 1.0 / n, 37, threads=threads)
+    assert used == threads and np.array_equal(a, b)
+    a = oracle.ks(u, 0.005, 0.5, 11)
+    b, used = oracle.ks_mt(u, 0.005, 0.5, 11, threads=threads)
+    assert used == threads and np.array_equal(a, b)
