@@ -18,9 +18,11 @@
  * Checking aid: with SWEPT_DEBUG_POISON set (to anything but "" or "0")
  * when a plan, batch or adjoint plan is created, its edge slots (and the
  * adjoints' checkpoints and lambda slots) are filled with quiet NaNs before
- * each run, so an entry read before a phase wrote it shows up as NaN in the
- * result.  Results are unchanged otherwise; the fill costs one pass over the
- * workspace per run.
+ * each run, and each tile's LDS buffers (band buffer, staging row, tier rows,
+ * halo exchange words) are filled with quiet NaNs when the tile starts, so an
+ * entry read before a phase or tile wrote it shows up as NaN in the result.
+ * Results are unchanged otherwise; the fill costs one pass over the workspace
+ * per run.
  *
  * Schemes (Sec. 4.1 and Appendix; periodic boundaries, index (i+k) mod n,
  * except for the insulated rod):
@@ -67,6 +69,13 @@ extern "C" {
 #define SWEPT_EUNSUPPORTED -2  /* valid request this build cannot tile       */
 #define SWEPT_ENOMEM -3        /* device allocation failed                   */
 #define SWEPT_EDEVICE -4       /* HIP runtime error (message in last_error)  */
+#define SWEPT_ENONFINITE -5    /* the opt-in check found a non-finite value  */
+/* There is no time-out status: no kernel of this library waits on another
+   workgroup or on the host (the batched kernel's workgroups only take work
+   from a counter and never spin), so every launch ends on its own. */
+
+/* check flags (swept_plan_set_checks, swept_batch_set_checks) */
+#define SWEPT_CHECK_NONFINITE 1 /* after each run, scan the grid for NaN/Inf */
 
 /* stencil kinds */
 #define SWEPT_HEAT_FTCS 0
@@ -190,6 +199,20 @@ int swept_plan_info(swept_plan p, int* tile_width, int* steps_per_cycle, size_t*
  * of swept_plan_create also fails with EUNSUPPORTED.
  */
 int swept_plan_set_engine(swept_plan p, int engine);
+
+/*
+ * swept_plan_set_checks -- opt-in checks of the plan's runs (0 = none, the
+ * default).  With SWEPT_CHECK_NONFINITE, swept_run and naive_run enqueue,
+ * after their phases, a scan of the n values of u that sets a plan-owned
+ * device flag when any value is NaN or infinite (the scheme itself never
+ * makes one from finite data unless it is unstable, e.g. Fo > 1/2), then wait
+ * for their stream and return SWEPT_ENONFINITE if the flag is set; u holds
+ * the run's result either way.  With the check on, runs are therefore
+ * synchronous and cannot be captured into a graph.  The first call with the
+ * flag allocates the 4-byte flag.  Errors: EINVAL (NULL plan, unknown flags),
+ * ENOMEM.
+ */
+int swept_plan_set_checks(swept_plan p, int flags);
 
 /* swept_plan_destroy -- free the plan and its workspace (NULL is a no-op). */
 void swept_plan_destroy(swept_plan p);
@@ -337,6 +360,15 @@ int swept_batch_set_engine(swept_batch b, int engine);
  * nprob entries, may be NULL), edge-slot bytes and persistent grid size.
  */
 int swept_batch_info(swept_batch b, int64_t* total_points, int64_t* offsets, size_t* workspace_bytes, int* grid);
+
+/*
+ * swept_batch_set_checks -- as swept_plan_set_checks for a batch: with
+ * SWEPT_CHECK_NONFINITE the scan of all grids' values is part of each run
+ * (of the captured graph too), and swept_batch_run waits for its stream and
+ * returns SWEPT_ENONFINITE when any grid holds a NaN or infinite value.
+ * Changing the flags drops a captured graph.  Errors: EINVAL, ENOMEM.
+ */
+int swept_batch_set_checks(swept_batch b, int flags);
 
 /* swept_batch_destroy -- free the plan and its device memory (NULL is a no-op). */
 void swept_batch_destroy(swept_batch b);

@@ -18,6 +18,8 @@ SWEPT_EINVAL = -1
 SWEPT_EUNSUPPORTED = -2
 SWEPT_ENOMEM = -3
 SWEPT_EDEVICE = -4
+SWEPT_ENONFINITE = -5
+SWEPT_CHECK_NONFINITE = 1
 
 SWEPT_HEAT_FTCS = 0
 SWEPT_HEAT_INSULATED = 2
@@ -56,6 +58,7 @@ def _declare(lib):
     lib.swept_run_noalloc.argtypes = [i64, i32, i32, dbl, dbl, dbl, i32, i32, vp, i64, vp]
     lib.swept_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(sz)]
     lib.swept_plan_set_engine.argtypes = [vp, i32]
+    lib.swept_plan_set_checks.argtypes = [vp, i32]
     lib.swept_plan_destroy.argtypes = [vp]
     lib.swept_plan_destroy.restype = None
     lib.swept_last_error.argtypes = []
@@ -74,6 +77,7 @@ def _declare(lib):
     lib.swept_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, pl, i32, i32, pd, pd, pd, i64]
     lib.swept_batch_run.argtypes = [vp, vp, i32, vp]
     lib.swept_batch_set_engine.argtypes = [vp, i32]
+    lib.swept_batch_set_checks.argtypes = [vp, i32]
     lib.swept_batch_info.argtypes = [vp, pl, pl, ctypes.POINTER(sz), pi]
     lib.swept_batch_destroy.argtypes = [vp]
     lib.swept_batch_destroy.restype = None
@@ -92,7 +96,7 @@ def _declare(lib):
     for name in ("swept_ks_adjoint_create", "swept_ks_forward_ckpt", "swept_ks_adjoint_run",
                  "swept_ks_adjoint_info", "swept_adjoint_create", "swept_forward_ckpt", "swept_adjoint_run", "swept_adjoint_info",
                  "swept_batch_create", "swept_batch_run", "swept_batch_set_engine", "swept_batch_info", "swept_autotune", "swept_autotune_lookup", "swept_tile_geometry", "swept_plan_create", "swept_run", "swept_run_noalloc", "naive_run", "swept_plan_info",
-                 "swept_plan_set_engine", "swept_schedule"):
+                 "swept_plan_set_engine", "swept_schedule", "swept_plan_set_checks", "swept_batch_set_checks"):
         getattr(lib, name).restype = i32
     return lib
 

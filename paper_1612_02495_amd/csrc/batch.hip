@@ -59,7 +59,8 @@ __global__ void batch_reset_kernel(int* queue) { *queue = 0; }
 // COMPACT: 0 register engine, 1 compacted engine.
 template <int KIND, typename T, int P, int NW, int COMPACT>
 __global__ void __launch_bounds__(64 * NW)
-batch_kernel(const BatchItem<T>* __restrict__ items, int nitems, T* u, T* slots, int64_t tiers, int* queue) {
+batch_kernel(const BatchItem<T>* __restrict__ items, int nitems, T* u, T* slots, int64_t tiers, int* queue,
+             int poison) {
   constexpr int S = Radius<KIND>::value;
   constexpr int SLEN = 64 * P + 2 * S;
   constexpr int NB = COMPACT ? compact::Lds<KIND, P>::band : 1;
@@ -97,6 +98,12 @@ batch_kernel(const BatchItem<T>* __restrict__ items, int nitems, T* u, T* slots,
         T* sL = parity ? slotB + (int64_t)j * SLEN : slotA + (int64_t)j * SLEN;
         T* sR = parity ? slotA + (int64_t)((j + 1) % pr.nt) * SLEN : slotB + (int64_t)j * SLEN;
         if constexpr (COMPACT) {
+          if (poison) {
+            // this tile's use of the wave's LDS starts from NaN
+            poison_lds(sbm[wave], NB, lane, 64);
+            poison_lds(stgm[wave], NS, lane, 64);
+            compact::wave_sync();
+          }
           compact::tile_phase_g<KIND, T, P>(ring, pr.n, compact::uneven_origin(ut, iL), sL, sR,
                                             compact::uneven_width(ut, iL), compact::uneven_width(ut, iR), hv, hl,
                                             pr.k, lane, sbm[wave], stgm[wave]);
@@ -292,8 +299,12 @@ __device__ __forceinline__ void resident_body(const BatchItem<T>& pr, T* u, int6
 
 template <int KIND, typename T, int NW>
 __global__ void __launch_bounds__(64 * NW)
-resident_kernel(const BatchItem<T>* __restrict__ items, T* u, int64_t steps) {
+resident_kernel(const BatchItem<T>* __restrict__ items, T* u, int64_t steps, int poison) {
   __shared__ ResLds<T, NW, 2> L;
+  if (poison) {
+    poison_lds(reinterpret_cast<T*>(&L), (int)(sizeof(L) / sizeof(T)), (int)threadIdx.x, 64 * NW);
+    __syncthreads();
+  }
   const BatchItem<T> pr = items[blockIdx.x];
   // points in the ring's last lane (workgroup-uniform)
   switch (pr.n - (pr.n - 1) / kResQ * kResQ) {
@@ -348,7 +359,9 @@ struct swept_batch_s {
   int* queue = nullptr;
   int device = 0;
   int engine = SWEPT_ENGINE_AUTO;
-  bool poison = false;             // SWEPT_DEBUG_POISON: NaN-fill the slots before each run
+  bool poison = false;             // SWEPT_DEBUG_POISON: NaN-fill the slots (and LDS) before each run
+  int checks = 0;                  // SWEPT_CHECK_* flags (swept_batch_set_checks)
+  int* flag = nullptr;             // device flag of the non-finite check
   int grid = 0;
   hipStream_t cap_stream = nullptr;
   hipStream_t side[swept::kResStreams] = {};  // branches of the resident classes, beside the persistent kernel
@@ -397,7 +410,7 @@ template <int KIND, typename T, int P, int C>
 void launch_batch(const swept_batch_s* b, void* u, int64_t tiers, hipStream_t st) {
   hipLaunchKernelGGL((swept::batch_kernel<KIND, T, P, swept::kBatchNW, C>), dim3((unsigned)b->grid),
                      dim3(64 * swept::kBatchNW), 0, st, static_cast<const BatchItem<T>*>(b->items), b->nswept,
-                     static_cast<T*>(u), static_cast<T*>(b->slots), tiers, b->queue);
+                     static_cast<T*>(u), static_cast<T*>(b->slots), tiers, b->queue, (int)b->poison);
 }
 
 // Launch the resident grids of size class cl (0: 16 waves, 1: 8, 2: 4, 3: 1).
@@ -411,16 +424,20 @@ void launch_resident(const swept_batch_s* b, int cl, void* u, hipStream_t st) {
   const dim3 grid((unsigned)cnt), block((unsigned)(64 * swept::kResWaves[cl]));
   if (cl == 0)
     hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[0]>), grid, block, 0, st, items + first,
-                       static_cast<T*>(u), b->steps);
+                       static_cast<T*>(u), b->steps,
+                       (int)b->poison);
   else if (cl == 1)
     hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[1]>), grid, block, 0, st, items + first,
-                       static_cast<T*>(u), b->steps);
+                       static_cast<T*>(u), b->steps,
+                       (int)b->poison);
   else if (cl == 2)
     hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[2]>), grid, block, 0, st, items + first,
-                       static_cast<T*>(u), b->steps);
+                       static_cast<T*>(u), b->steps,
+                       (int)b->poison);
   else
     hipLaunchKernelGGL((swept::resident_kernel<KIND, T, swept::kResWaves[3]>), grid, block, 0, st, items + first,
-                       static_cast<T*>(u), b->steps);
+                       static_cast<T*>(u), b->steps,
+                       (int)b->poison);
 }
 
 template <int P, int C>
@@ -472,7 +489,18 @@ hipError_t launch_swept(swept_batch_s* b, void* u, hipStream_t st);
 // graph), beside the persistent kernel on `st`.  Run one after another, the
 // classes would end well after the persistent kernel (heat: 65.7 ms against
 // 52.0 ms).
+hipError_t enqueue_runs(swept_batch_s* b, void* u, hipStream_t st);
+
+// The batch's launches, then (with the non-finite check on) the scan of every
+// grid's values.
 hipError_t enqueue_batch(swept_batch_s* b, void* u, hipStream_t st) {
+  hipError_t e = enqueue_runs(b, u, st);
+  if (e == hipSuccess && (b->checks & SWEPT_CHECK_NONFINITE))
+    e = swept::enqueue_nonfinite_check(u, b->total_points, b->dtype == SWEPT_F64 ? 8 : 4, b->flag, st);
+  return e;
+}
+
+hipError_t enqueue_runs(swept_batch_s* b, void* u, hipStream_t st) {
   if (b->nres == 0) return launch_swept(b, u, st);
   bool used[swept::kResStreams] = {};
   for (int cl = 0; cl < swept::kResClasses; ++cl)
@@ -711,6 +739,7 @@ void batch_free(swept_batch_s* b) {
   if (b->res_items) (void)hipFree(b->res_items);
   if (b->slots) (void)hipFree(b->slots);
   if (b->queue) (void)hipFree(b->queue);
+  if (b->flag) (void)hipFree(b->flag);
   delete b;
 }
 
@@ -855,8 +884,37 @@ int swept_batch_run(swept_batch b, void* u, int use_graph, void* stream) {
       if (e != hipSuccess) rc = bhip(e, "hipGraphLaunch");
     }
   }
+  if (rc == SWEPT_OK && (b->checks & SWEPT_CHECK_NONFINITE)) {
+    int bad = 0;
+    e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemcpy(&bad, b->flag, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+      rc = bhip(e, "non-finite check");
+    else if (bad)
+      rc = bfail(SWEPT_ENONFINITE, "a grid holds a non-finite value after the run");
+  }
   if (prev != b->device) (void)hipSetDevice(prev);
   return rc;
+}
+
+int swept_batch_set_checks(swept_batch b, int flags) {
+  if (!b) return bfail(SWEPT_EINVAL, "batch must not be NULL");
+  if (flags & ~SWEPT_CHECK_NONFINITE) return bfail(SWEPT_EINVAL, "unknown check flags");
+  if (flags == b->checks) return SWEPT_OK;
+  if ((flags & SWEPT_CHECK_NONFINITE) && !b->flag) {
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e == hipSuccess && prev != b->device) e = hipSetDevice(b->device);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->flag), sizeof(int));
+    if (prev >= 0 && prev != b->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+      b->flag = nullptr;
+      return bfail(SWEPT_ENOMEM, std::string("hipMalloc(check flag): ") + hipGetErrorString(e));
+    }
+  }
+  b->checks = flags;
+  drop_graph(b);  // the captured launches include (or not) the check
+  return SWEPT_OK;
 }
 
 int swept_batch_info(swept_batch b, int64_t* total_points, int64_t* offsets, size_t* workspace_bytes, int* grid) {

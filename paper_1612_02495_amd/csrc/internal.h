@@ -31,6 +31,7 @@ struct PhaseArgs {
   int parity;    // 0: tiles start at j*w; 1: at j*w + w/2
   int hv;        // V height in tiers (0 = load full row)
   int hl;        // Lambda height in tiers (0 = store full row)
+  int poison = 0;  // fill the tile's LDS with NaN first (SWEPT_DEBUG_POISON)
 };
 
 // Values per edge slot: (w/2 + s) positions, two tier parities each.

@@ -4,6 +4,7 @@
 // Tiles, slots and phase parities are those of the other engines, so all
 // three can run alternate phases of one run.
 #include "compact_tile.h"
+#include "poison.h"
 
 namespace swept {
 namespace {
@@ -25,13 +26,18 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nt) {
 // (parity 0).  Only those tiles run the tier code with the mirror ghosts.
 template <int KIND, typename T, int P, int ROLE, bool INS>
 __global__ void __launch_bounds__(64)
-phase_compact_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, int hl, Consts<T> k) {
+phase_compact_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, int hl, Consts<T> k, int poison) {
   constexpr int S = Radius<KIND>::value;
   constexpr int W = 64 * P;
   constexpr int HALF = 32 * P;
   constexpr int SLEN = W + 2 * S;
   __shared__ T sb[compact::Lds<KIND, P>::band];
   __shared__ T stg[compact::Lds<KIND, P>::stage];
+  if (poison) {
+    poison_lds(sb, compact::Lds<KIND, P>::band, (int)threadIdx.x, 64);
+    poison_lds(stg, compact::Lds<KIND, P>::stage, (int)threadIdx.x, 64);
+    compact::wave_sync();
+  }
   const int64_t j = KIND == kHeat ? xcd_tile(blockIdx.x, nt) : (int64_t)blockIdx.x;
   const int64_t origin = j * (int64_t)W + (parity ? HALF : 0);
   T* sL = parity ? slots + (nt + j) * SLEN : slots + j * SLEN;
@@ -54,7 +60,7 @@ hipError_t launch_p(const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
   auto kern = a.hv == 0 ? phase_compact_kernel<KIND, T, P, 0, INS>
               : (a.hl == 0 ? phase_compact_kernel<KIND, T, P, 2, INS> : phase_compact_kernel<KIND, T, P, 1, INS>);
   hipLaunchKernelGGL(kern, dim3((unsigned)a.nt), dim3(64), 0, st, static_cast<T*>(a.u), static_cast<T*>(a.slots),
-                     a.n, a.nt, a.parity, a.hv, a.hl, k);
+                     a.n, a.nt, a.parity, a.hv, a.hl, k, a.poison);
   return hipGetLastError();
 }
 

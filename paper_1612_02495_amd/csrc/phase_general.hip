@@ -11,17 +11,23 @@
 // height of the smallest half (Sec. 4.2; flattened tops on the wider halves,
 // Sec. 4.3).
 #include "compact_tile.h"
+#include "poison.h"
 
 namespace swept {
 namespace {
 
 template <int KIND, typename T, int P>
 __global__ void __launch_bounds__(64)
-phase_general_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, int hl, Consts<T> k) {
+phase_general_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, int hl, Consts<T> k, int poison) {
   constexpr int S = Radius<KIND>::value;
   constexpr int SLEN = 64 * P + 2 * S;
   __shared__ T sb[compact::Lds<KIND, P>::band];
   __shared__ T stg[compact::Lds<KIND, P>::stage];
+  if (poison) {
+    poison_lds(sb, compact::Lds<KIND, P>::band, (int)threadIdx.x, 64);
+    poison_lds(stg, compact::Lds<KIND, P>::stage, (int)threadIdx.x, 64);
+    compact::wave_sync();
+  }
   const int64_t j = blockIdx.x;
   const compact::Uneven ut = compact::uneven_tiling(n, P, S);
   const int64_t iL = 2 * j + parity;
@@ -35,7 +41,7 @@ phase_general_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, 
 template <int KIND, typename T, int P>
 hipError_t launch_p(const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
   hipLaunchKernelGGL((phase_general_kernel<KIND, T, P>), dim3((unsigned)a.nt), dim3(64), 0, st,
-                     static_cast<T*>(a.u), static_cast<T*>(a.slots), a.n, a.nt, a.parity, a.hv, a.hl, k);
+                     static_cast<T*>(a.u), static_cast<T*>(a.slots), a.n, a.nt, a.parity, a.hv, a.hl, k, a.poison);
   return hipGetLastError();
 }
 

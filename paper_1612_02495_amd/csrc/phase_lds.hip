@@ -18,6 +18,7 @@
 // slots completely before it writes them, and no other tile touches them
 // during the phase, so the strips are updated in place.
 #include "internal.h"
+#include "poison.h"
 
 namespace swept {
 namespace {
@@ -42,12 +43,16 @@ __device__ __forceinline__ void tier_update(T* __restrict__ dst, const T* __rest
 template <int KIND, typename T, int ROLE>
 __global__ void __launch_bounds__(kLdsThreads)
 phase_lds_kernel(T* __restrict__ u, T* __restrict__ slots, int64_t n, int w, int64_t nt, int parity,
-                 int hv, int hl, Consts<T> k) {
+                 int hv, int hl, Consts<T> k, int poison) {
   constexpr int S = Radius<KIND>::value;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const int rowlen = w + 2 * S;
   const int slen = slot_values(w, S);
+  if (poison) {
+    poison_lds(smem, 2 * rowlen + 2 * slen, (int)threadIdx.x, (int)blockDim.x);
+    __syncthreads();
+  }
   T* row[2] = {smem + S, smem + rowlen + S};  // index x in [-S, w + S)
   T* inL = smem + 2 * rowlen;
   T* inR = inL + slen;
@@ -164,7 +169,7 @@ hipError_t launch_phase_lds(const PhaseArgs& a, const Consts<T>& k, hipStream_t 
   auto kern = a.hv == 0 ? phase_lds_kernel<KIND, T, 0>
               : (a.hl == 0 ? phase_lds_kernel<KIND, T, 2> : phase_lds_kernel<KIND, T, 1>);
   hipLaunchKernelGGL(kern, dim3((unsigned)a.nt), dim3(threads), lds, st, static_cast<T*>(a.u),
-                     static_cast<T*>(a.slots), a.n, a.w, a.nt, a.parity, a.hv, a.hl, k);
+                     static_cast<T*>(a.slots), a.n, a.w, a.nt, a.parity, a.hv, a.hl, k, a.poison);
   return hipGetLastError();
 }
 

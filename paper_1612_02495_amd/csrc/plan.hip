@@ -116,7 +116,9 @@ struct swept_plan_s {
   size_t slots_bytes = 0;
   void* buf = nullptr;  // naive ping-pong / predictor buffer
   size_t buf_bytes = 0;
-  bool poison = false;  // SWEPT_DEBUG_POISON: NaN-fill the slots before each run
+  bool poison = false;  // SWEPT_DEBUG_POISON: NaN-fill the slots (and the tiles' LDS) before each run
+  int checks = 0;       // SWEPT_CHECK_* flags (swept_plan_set_checks)
+  int* flag = nullptr;  // device flag of the non-finite check
   Consts<double> kd{};
   Consts<float> kf{};
 };
@@ -333,7 +335,7 @@ int plan_setup(swept_plan_s* p, int64_t n, int kind, int dtype, double dt, doubl
 // Enqueue the launches of one swept run of p on st with `slots` as the edge
 // slots: an up-triangle phase, the diamond phases and a down-triangle phase;
 // full phases of p->h tiers, the remainder last.  Nothing is allocated.
-int enqueue_swept(const swept_plan_s* p, void* slots, void* u, int64_t steps, hipStream_t st) {
+int enqueue_swept(const swept_plan_s* p, void* slots, void* u, int64_t steps, hipStream_t st, bool poison) {
   const int64_t tiers = steps * tiers_per_step(p->kind);
   const int64_t full = tiers / p->h;
   const int rem = (int)(tiers % p->h);
@@ -348,11 +350,24 @@ int enqueue_swept(const swept_plan_s* p, void* slots, void* u, int64_t steps, hi
     a.parity = (int)(i & 1);
     a.hv = i == 0 ? 0 : (i - 1 < full ? p->h : rem);
     a.hl = i == nedge ? 0 : (i < full ? p->h : rem);
+    a.poison = poison ? 1 : 0;
     hipError_t err = p->dtype == SWEPT_F64 ? dispatch_phase<double>(p, a, p->kd, st)
                                            : dispatch_phase<float>(p, a, p->kf, st);
     if (err != hipSuccess) return hip_fail(err, "swept phase launch");
   }
   return SWEPT_OK;
+}
+
+// With the non-finite check on, scan u after the run, wait for the stream and
+// report SWEPT_ENONFINITE if any value is not finite.
+int finish_run(const swept_plan_s* p, const void* u, hipStream_t st) {
+  if (!(p->checks & SWEPT_CHECK_NONFINITE)) return SWEPT_OK;
+  hipError_t e = swept::enqueue_nonfinite_check(u, p->n, (int)elem_size(p->dtype), p->flag, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  int bad = 0;
+  if (e == hipSuccess) e = hipMemcpy(&bad, p->flag, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "non-finite check");
+  return bad ? fail(SWEPT_ENONFINITE, "the grid holds a non-finite value after the run") : SWEPT_OK;
 }
 
 constexpr int kMaxDevices = 64;
@@ -469,6 +484,7 @@ void swept_plan_destroy(swept_plan p) {
   swept::DeviceGuard g(p->device);
   if (p->slots) (void)hipFree(p->slots);
   if (p->buf) (void)hipFree(p->buf);
+  if (p->flag) (void)hipFree(p->flag);
   delete p;
 }
 
@@ -484,7 +500,8 @@ int swept_run(swept_plan p, void* u, int64_t steps, void* stream) {
     const hipError_t pe = swept::poison_fill(p->slots, p->slots_bytes, (int)elem_size(p->dtype), st);
     if (pe != hipSuccess) return hip_fail(pe, "workspace poison fill");
   }
-  return enqueue_swept(p, p->slots, u, steps, st);
+  const int rc = enqueue_swept(p, p->slots, u, steps, st, p->poison);
+  return rc != SWEPT_OK ? rc : finish_run(p, u, st);
 }
 
 int swept_run_noalloc(int64_t n, int kind, int dtype, double dt, double dx, double alpha, int tile_width,
@@ -499,11 +516,12 @@ int swept_run_noalloc(int64_t n, int kind, int dtype, double dt, double dx, doub
   rc = scratch_address(p.device, &slots);
   if (rc != SWEPT_OK) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (swept::debug_poison_requested()) {
+  const bool poison = swept::debug_poison_requested();
+  if (poison) {
     const hipError_t pe = swept::poison_fill(slots, p.slots_bytes, (int)elem_size(p.dtype), st);
     if (pe != hipSuccess) return hip_fail(pe, "workspace poison fill");
   }
-  return enqueue_swept(&p, slots, u, steps, st);
+  return enqueue_swept(&p, slots, u, steps, st, poison);
 }
 
 int naive_run(swept_plan p, void* u, int64_t steps, void* stream) {
@@ -517,6 +535,22 @@ int naive_run(swept_plan p, void* u, int64_t steps, void* stream) {
   hipError_t err = p->dtype == SWEPT_F64 ? run_naive<double>(p, static_cast<double*>(u), steps, p->kd, st)
                                          : run_naive<float>(p, static_cast<float*>(u), steps, p->kf, st);
   if (err != hipSuccess) return hip_fail(err, "naive launch");
+  return finish_run(p, u, st);
+}
+
+int swept_plan_set_checks(swept_plan p, int flags) {
+  if (!p) return fail(SWEPT_EINVAL, "plan must not be NULL");
+  if (flags & ~SWEPT_CHECK_NONFINITE) return fail(SWEPT_EINVAL, "unknown check flags");
+  if ((flags & SWEPT_CHECK_NONFINITE) && !p->flag) {
+    swept::DeviceGuard g(p->device);
+    if (!g.ok) return hip_fail(g.err, "hipSetDevice");
+    const hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->flag), sizeof(int));
+    if (e != hipSuccess) {
+      p->flag = nullptr;
+      return fail(SWEPT_ENOMEM, std::string("hipMalloc(check flag): ") + hipGetErrorString(e));
+    }
+  }
+  p->checks = flags;
   return SWEPT_OK;
 }
 

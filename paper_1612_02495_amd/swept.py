@@ -78,6 +78,10 @@ def swept_plan_set_engine(plan, engine) -> None:
     check(_lib.lib().swept_plan_set_engine(plan, e))
 
 
+def swept_plan_set_checks(plan, flags: int) -> None:
+    check(_lib.lib().swept_plan_set_checks(plan, int(flags)))
+
+
 def swept_plan_destroy(plan) -> None:
     if plan:
         _lib.lib().swept_plan_destroy(plan)
@@ -167,6 +171,10 @@ def swept_batch_set_engine(batch, engine) -> None:
     check(_lib.lib().swept_batch_set_engine(batch, e))
 
 
+def swept_batch_set_checks(batch, flags: int) -> None:
+    check(_lib.lib().swept_batch_set_checks(batch, int(flags)))
+
+
 def swept_batch_info(batch, nprob: int) -> dict:
     tot, ws, grid = ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_int()
     offs = np.zeros(nprob, dtype=np.int64)
@@ -203,6 +211,11 @@ class Batch:
         grid) or 'auto' (the default, the same as 'resident')."""
         swept_batch_set_engine(self._h, engine)
         self.grid = swept_batch_info(self._h, self.n.size)["grid"]
+        return self
+
+    def set_checks(self, nonfinite: bool = True):
+        """Opt-in check of every grid for NaN or Inf after each run."""
+        swept_batch_set_checks(self._h, _lib.SWEPT_CHECK_NONFINITE if nonfinite else 0)
         return self
 
     def run(self, u, use_graph: bool = True, stream=None):
@@ -476,6 +489,12 @@ class Plan:
     def set_engine(self, engine):
         swept_plan_set_engine(self._h, engine)
 
+    def set_checks(self, nonfinite: bool = True):
+        """Opt-in check: runs then wait for their stream and raise SweptError
+        (code SWEPT_ENONFINITE) when the grid holds NaN or Inf."""
+        swept_plan_set_checks(self._h, _lib.SWEPT_CHECK_NONFINITE if nonfinite else 0)
+        return self
+
     def info(self) -> dict:
         return swept_plan_info(self._h)
 
@@ -498,7 +517,7 @@ class Plan:
 
 
 __all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "swept_run_noalloc", "naive_run", "swept_plan_info",
-           "swept_plan_set_engine", "swept_plan_destroy", "swept_last_error", "swept_schedule",
+           "swept_plan_set_engine", "swept_plan_set_checks", "swept_batch_set_checks", "swept_plan_destroy", "swept_last_error", "swept_schedule",
            "swept_tile_geometry", "swept_autotune", "swept_autotune_lookup", "swept_autotune_forget",
            "Batch", "swept_batch_create", "swept_batch_run", "swept_batch_set_engine", "swept_batch_info",
            "swept_batch_destroy",

@@ -189,3 +189,18 @@ def test_noalloc_size_limit_message():
     assert _noalloc(n=1 << 22, w=1024) == _lib.SWEPT_EUNSUPPORTED
     msg = P.swept_last_error()
     assert "static workspace" in msg and str(2 * 4096 * 1026 * 8) in msg
+
+
+def test_check_flags_validated_before_any_device_call():
+    lib = _lib.lib()
+    assert lib.swept_plan_set_checks(None, _lib.SWEPT_CHECK_NONFINITE) == _lib.SWEPT_EINVAL
+    assert lib.swept_batch_set_checks(None, _lib.SWEPT_CHECK_NONFINITE) == _lib.SWEPT_EINVAL
+    assert _lib.SWEPT_ENONFINITE == -5
+
+
+def test_header_documents_status_codes():
+    text = open(HEADER).read()
+    for name, code in (("SWEPT_OK", 0), ("SWEPT_EINVAL", -1), ("SWEPT_EUNSUPPORTED", -2), ("SWEPT_ENOMEM", -3),
+                       ("SWEPT_EDEVICE", -4), ("SWEPT_ENONFINITE", -5)):
+        assert re.search(rf"#define {name} {code}\b", text), name
+    assert "no time-out status" in text
