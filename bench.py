@@ -460,6 +460,20 @@ def run_adjoint(args, wl):
         w = plan.info["tile_width"]
         flops = B * (n // w) * w * h * (4 + 4 + 5)
         roof = roofline("fused reverse region launch (recompute + lambda + dJ/dalpha)", flops, t_launch, "f64")
+    # the same gradient with two-level checkpointing (about sqrt(K) phases per
+    # segment: every segment-th phase's edge state kept, the rest recomputed)
+    two = None
+    if not args.no_two_level:
+        p2 = AdjointPlan(B, n, dt, dx, T, segment=0)
+
+        def step2():
+            p2.forward(du0, dal, uT)
+            p2.adjoint(uT - y, g_u0, g_a)
+        step2()
+        t2 = _time_runs(step2, args.steps, torch)
+        two = {"adjoint_grad_ms": 1e3 * t2 / args.steps, "checkpoint_bytes": p2.info["checkpoint_bytes"],
+               "time_vs_all_phases_kept": t2 / t}
+        p2.close()
     cpu = None
     if not args.no_cpu_baseline:
         cs = args.cpu_steps or 1500
@@ -474,7 +488,8 @@ def run_adjoint(args, wl):
                    "adjoint_grad_ms": 1e3 * t / args.steps, "forward_ckpt_ms": 1e3 * t_fwd / args.steps,
                    "checkpoint_bytes": plan.info["checkpoint_bytes"],
                    "tile_width": plan.info["tile_width"], "steps_per_cycle": plan.info["steps_per_cycle"],
-                   "leading_classic_steps": plan.info["leading_classic_steps"], "parallelism": "single GPU"},
+                   "leading_classic_steps": plan.info["leading_classic_steps"], "parallelism": "single GPU",
+                   "two_level_checkpointing": two},
         "roofline": roof, "naive": None, "speedup_vs_naive": None, "cpu_baseline": cpu,
     }
     plan.close()
@@ -638,6 +653,8 @@ def main(argv=None):
     ap.add_argument("--no-nested", action="store_true",
                     help="measure the chosen workload only (no nested KS, batch and gradient records)")
     ap.add_argument("--batch", type=int, default=0, help="grids in the adjoint workloads (0 = 64 heat, 1 KS)")
+    ap.add_argument("--no-two-level", action="store_true",
+                    help="skip the two-level checkpointing timing of the heat gradient")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args(argv)

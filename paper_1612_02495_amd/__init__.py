@@ -13,7 +13,7 @@ from .swept import (Plan, SweptError, naive_run, swept_last_error, swept_plan_cr
                     swept_batch_destroy, AdjointPlan, swept_heat, swept_adjoint_create, swept_forward_ckpt,
                     swept_adjoint_run, swept_adjoint_info, swept_adjoint_destroy, KsAdjointPlan, swept_ks,
                     swept_ks_adjoint_create, swept_ks_forward_ckpt, swept_ks_adjoint_run, swept_ks_adjoint_info,
-                    swept_ks_adjoint_destroy)
+                    swept_ks_adjoint_destroy, release_cached_plans)
 
 __all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "swept_run_noalloc", "naive_run",
            "swept_plan_info", "swept_plan_set_engine", "swept_plan_set_checks", "swept_batch_set_checks",
@@ -24,4 +24,4 @@ __all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "swept_run_no
            "AdjointPlan", "swept_heat", "swept_adjoint_create", "swept_forward_ckpt", "swept_adjoint_run",
            "swept_adjoint_info", "swept_adjoint_destroy", "KsAdjointPlan", "swept_ks",
            "swept_ks_adjoint_create", "swept_ks_forward_ckpt", "swept_ks_adjoint_run", "swept_ks_adjoint_info",
-           "swept_ks_adjoint_destroy"]
+           "swept_ks_adjoint_destroy", "release_cached_plans"]

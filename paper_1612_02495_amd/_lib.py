@@ -82,6 +82,7 @@ def _declare(lib):
     lib.swept_batch_destroy.argtypes = [vp]
     lib.swept_batch_destroy.restype = None
     lib.swept_adjoint_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, i64, i32, dbl, dbl, i64]
+    lib.swept_adjoint_create_segmented.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, i64, i32, dbl, dbl, i64, i32]
     lib.swept_forward_ckpt.argtypes = [vp, vp, vp, vp, vp]
     lib.swept_adjoint_run.argtypes = [vp, vp, vp, vp, vp]
     lib.swept_adjoint_info.argtypes = [vp, ctypes.POINTER(sz), pi, pi, pl]
@@ -94,7 +95,7 @@ def _declare(lib):
     lib.swept_ks_adjoint_destroy.argtypes = [vp]
     lib.swept_ks_adjoint_destroy.restype = None
     for name in ("swept_ks_adjoint_create", "swept_ks_forward_ckpt", "swept_ks_adjoint_run",
-                 "swept_ks_adjoint_info", "swept_adjoint_create", "swept_forward_ckpt", "swept_adjoint_run", "swept_adjoint_info",
+                 "swept_ks_adjoint_info", "swept_adjoint_create", "swept_adjoint_create_segmented", "swept_forward_ckpt", "swept_adjoint_run", "swept_adjoint_info",
                  "swept_batch_create", "swept_batch_run", "swept_batch_set_engine", "swept_batch_info", "swept_autotune", "swept_autotune_lookup", "swept_tile_geometry", "swept_plan_create", "swept_run", "swept_run_noalloc", "naive_run", "swept_plan_info",
                  "swept_plan_set_engine", "swept_schedule", "swept_plan_set_checks", "swept_batch_set_checks"):
         getattr(lib, name).restype = i32

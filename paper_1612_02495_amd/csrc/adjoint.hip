@@ -475,7 +475,10 @@ struct swept_adjoint_s {
   bool have_forward = false;
   bool poison = false;        // SWEPT_DEBUG_POISON: NaN-fill checkpoints and lambda slots before use
   double* consts = nullptr;   // Consts<double>[batch]
-  double* ckpt = nullptr;     // K phases x batch x 2nt x 66
+  int Q = 1;                  // phases per checkpoint segment (1: every phase's edge state kept)
+  int nlev = 0;               // kept checkpoint sets: phases 0, Q, 2Q, .. below K
+  double* ckpt = nullptr;     // nlev kept sets, then Q-1 sets of the segment being recomputed;
+                              // a set is batch x 2nt x 66 values
   double* lam_slots = nullptr;
   double* rem = nullptr;      // (r+1) states x batch x n: u_0 .. u_r
   double* lam_a = nullptr;    // batch x n
@@ -492,6 +495,30 @@ using swept::adj::kW;
 
 int afail(int code, const std::string& m) { return swept::set_error(code, m); }
 int ahip(hipError_t e, const char* what) { return afail(SWEPT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)); }
+
+// Where the edge state written by phase q (the reverse launch of phase q + 1
+// restarts from it) lives: the kept sets for q = 0, Q, 2Q, .., the segment
+// sets for the phases in between (rewritten segment by segment).
+double* ckpt_set(const swept_adjoint_s* a, int q) {
+  const size_t pslots = (size_t)a->batch * 2 * (size_t)a->nt * kSL;
+  if (q % a->Q == 0) return a->ckpt + (size_t)(q / a->Q) * pslots;
+  return a->ckpt + (size_t)(a->nlev + q % a->Q - 1) * pslots;
+}
+
+// Forward phases q0 .. q1 (all with both a V and a Lambda part) from the
+// edge state of phase q0 - 1, each writing its own edge state.
+hipError_t forward_phases(const swept_adjoint_s* a, int q0, int q1, hipStream_t st) {
+  constexpr int FP = swept::adj::kFwdPoints;
+  const auto* k = reinterpret_cast<const swept::Consts<double>*>(a->consts);
+  for (int q = q0; q <= q1; ++q) {
+    hipLaunchKernelGGL((swept::adj::forward_kernel<FP, true, true>), dim3((unsigned)((a->nt + FP - 1) / FP),
+                       (unsigned)a->batch), dim3(kW), 0, st, nullptr, nullptr, ckpt_set(a, q - 1), ckpt_set(a, q), k,
+                       a->n, a->nt, q);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 void adj_free(swept_adjoint_s* a) {
   for (double* q : {a->consts, a->ckpt, a->lam_slots, a->rem, a->lam_a, a->lam_b, a->tiles, a->rparts})
@@ -511,6 +538,11 @@ extern "C" {
 
 int swept_adjoint_create(swept_adjoint* out, int32_t batch, int64_t n, int dtype, double dt, double dx,
                          int64_t steps) {
+  return swept_adjoint_create_segmented(out, batch, n, dtype, dt, dx, steps, 1);
+}
+
+int swept_adjoint_create_segmented(swept_adjoint* out, int32_t batch, int64_t n, int dtype, double dt, double dx,
+                                   int64_t steps, int segment) {
   if (!out) return afail(SWEPT_EINVAL, "out must not be NULL");
   *out = nullptr;
   if (batch < 1 || batch > 65535) return afail(SWEPT_EINVAL, "batch must be in [1, 65535]");
@@ -518,6 +550,7 @@ int swept_adjoint_create(swept_adjoint* out, int32_t batch, int64_t n, int dtype
   if (n < kW || n % kW != 0) return afail(SWEPT_EUNSUPPORTED, "n must be a positive multiple of 64");
   if (steps < 1) return afail(SWEPT_EINVAL, "steps must be >= 1");
   if (!std::isfinite(dt) || !std::isfinite(dx) || dx == 0.0) return afail(SWEPT_EINVAL, "dt, dx must be finite, dx != 0");
+  if (segment < 0) return afail(SWEPT_EINVAL, "segment must be >= 0");
   // the remainder steps launch one work-item per point of the batch
   const int64_t nblk = (n + swept::adj::kRemThreads - 1) / swept::adj::kRemThreads;
   if ((int64_t)batch * nblk * swept::adj::kRemThreads > (int64_t)UINT32_MAX)
@@ -533,6 +566,15 @@ int swept_adjoint_create(swept_adjoint* out, int32_t batch, int64_t n, int dtype
   a->nblk = nblk;
   a->r = (int)(steps % swept::adj::kH);
   a->K = (int)(steps / swept::adj::kH);
+  // segment 0: about sqrt(K) phases per segment, which keeps about 2 sqrt(K)
+  // sets instead of K for one more forward pass
+  int Q = segment;
+  if (Q == 0) {
+    Q = 1;
+    while ((int64_t)Q * Q < a->K) ++Q;
+  }
+  a->Q = std::max(1, std::min(Q, std::max(1, a->K)));
+  a->nlev = a->K > 0 ? (a->K - 1) / a->Q + 1 : 0;
   a->poison = swept::debug_poison_requested();
   hipError_t e = hipGetDevice(&a->device);
   if (e != hipSuccess) {
@@ -541,7 +583,7 @@ int swept_adjoint_create(swept_adjoint* out, int32_t batch, int64_t n, int dtype
   }
   const size_t state = (size_t)batch * (size_t)n * sizeof(double);
   const size_t slots = (size_t)batch * 2 * (size_t)a->nt * kSL * sizeof(double);
-  a->ckpt_bytes = (size_t)a->K * slots;
+  a->ckpt_bytes = (size_t)(a->nlev + (a->Q > 1 ? a->Q - 1 : 0)) * slots;
   struct Alloc {
     double** p;
     size_t bytes;
@@ -587,13 +629,12 @@ int swept_forward_ckpt(swept_adjoint a, const void* u0, const double* alpha, voi
     e = hipGetLastError();
   }
   const double* ur = a->rem + (size_t)a->r * total;
-  const size_t pslots = (size_t)a->batch * 2 * (size_t)a->nt * kSL;
   if (a->K == 0) {
     if (e == hipSuccess) e = hipMemcpyAsync(uT, ur, state, hipMemcpyDeviceToDevice, st);
   } else {
     for (int p = 0; p <= a->K && e == hipSuccess; ++p) {
-      const double* ck_in = p > 0 ? a->ckpt + (size_t)(p - 1) * pslots : nullptr;
-      double* ck_out = p < a->K ? a->ckpt + (size_t)p * pslots : nullptr;
+      const double* ck_in = p > 0 ? ckpt_set(a, p - 1) : nullptr;
+      double* ck_out = p < a->K ? ckpt_set(a, p) : nullptr;
       constexpr int FP = swept::adj::kFwdPoints;
       auto kern = p == 0 ? swept::adj::forward_kernel<FP, false, true>
                   : (p == a->K ? swept::adj::forward_kernel<FP, true, false> : swept::adj::forward_kernel<FP, true, true>);
@@ -617,7 +658,6 @@ int swept_adjoint_run(swept_adjoint a, const void* g_uT, void* g_u0, double* g_a
   const int64_t total = (int64_t)a->batch * a->n;
   const size_t state = (size_t)total * sizeof(double);
   auto* k = reinterpret_cast<const swept::Consts<double>*>(a->consts);
-  const size_t pslots = (size_t)a->batch * 2 * (size_t)a->nt * kSL;
   hipError_t e = zero(a->tiles, (int64_t)a->batch * a->nt, st);
   if (e == hipSuccess) e = zero(a->rparts, (int64_t)a->batch * a->nblk, st);
   if (e == hipSuccess && a->poison)
@@ -629,7 +669,14 @@ int swept_adjoint_run(swept_adjoint a, const void* g_uT, void* g_u0, double* g_a
   } else {
     const double* ur = a->rem + (size_t)a->r * total;
     for (int p = a->K; p >= 0 && e == hipSuccess; --p) {
-      const double* ck_in = p > 0 ? a->ckpt + (size_t)(p - 1) * pslots : nullptr;
+      // entering a segment from its top: recompute the edge states of its
+      // phases from the kept state that starts it
+      if (a->Q > 1 && p >= 2 && (p == a->K || p % a->Q == 0)) {
+        const int q0 = (p - 1) / a->Q * a->Q + 1;
+        if (q0 <= p - 1) e = forward_phases(a, q0, p - 1, st);
+        if (e != hipSuccess) break;
+      }
+      const double* ck_in = p > 0 ? ckpt_set(a, p - 1) : nullptr;
       auto kern = p == 0 ? swept::adj::region_kernel<false, true>
                   : (p == a->K ? swept::adj::region_kernel<true, false> : swept::adj::region_kernel<true, true>);
       hipLaunchKernelGGL(kern, dim3((unsigned)a->nt, (unsigned)a->batch), dim3(kW), 0, st, ur, ck_in,

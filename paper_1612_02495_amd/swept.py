@@ -248,6 +248,14 @@ def swept_adjoint_create(batch: int, n: int, dtype, dt: float, dx: float, steps:
     return h
 
 
+def swept_adjoint_create_segmented(batch: int, n: int, dtype, dt: float, dx: float, steps: int,
+                                   segment: int = 0) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    check(_lib.lib().swept_adjoint_create_segmented(ctypes.byref(h), int(batch), int(n), _dtype_code(dtype),
+                                                    float(dt), float(dx), int(steps), int(segment)))
+    return h
+
+
 def swept_forward_ckpt(adj, u0, alpha, uT, stream=None) -> None:
     check(_lib.lib().swept_forward_ckpt(adj, ctypes.c_void_p(u0.data_ptr()), ctypes.c_void_p(alpha.data_ptr()),
                                         ctypes.c_void_p(uT.data_ptr()), _stream_ptr(u0, stream)))
@@ -273,10 +281,14 @@ def swept_adjoint_destroy(adj) -> None:
 class AdjointPlan:
     """Checkpointed swept forward and reverse sweep for a batch of heat grids."""
 
-    def __init__(self, batch: int, n: int, dt: float, dx: float, steps: int):
+    def __init__(self, batch: int, n: int, dt: float, dx: float, steps: int, segment: int = 1):
+        """segment: phases per checkpoint segment (1 keeps every phase's edge
+        state; 0 picks about sqrt(phases), two-level checkpointing)."""
         self.batch, self.n, self.steps = int(batch), int(n), int(steps)
-        self._h = swept_adjoint_create(batch, n, "f64", dt, dx, steps)
+        self._h = (swept_adjoint_create(batch, n, "f64", dt, dx, steps) if segment == 1
+                   else swept_adjoint_create_segmented(batch, n, "f64", dt, dx, steps, segment))
         self.info = swept_adjoint_info(self._h)
+        self.generation = 0  # forward passes run so far (each rewrites the checkpoints)
 
     def _check(self, t, shape):
         import torch
@@ -288,6 +300,7 @@ class AdjointPlan:
         self._check(alpha, (self.batch,))
         self._check(uT, (self.batch, self.n))
         swept_forward_ckpt(self._h, u0, alpha, uT, stream)
+        self.generation += 1
         return uT
 
     def adjoint(self, g_uT, g_u0, g_alpha, stream=None):
@@ -309,6 +322,47 @@ class AdjointPlan:
             pass
 
 
+# Adjoint plans kept between autograd calls.  A plan's checkpoints are large
+# (2.06 n x 8 bytes per grid per 32-step phase for heat, unless segmented),
+# so a training loop must not allocate them anew at every step.  The pool
+# holds plans whose checkpoints no pending backward needs: a forward takes a
+# free plan of its configuration (or makes one) and its backward puts it back.
+# Every forward bumps the plan's generation; a later backward of the same
+# graph (retain_graph, gradcheck) whose plan has since run another forward
+# recomputes its own forward, into a free plan, from the saved inputs.
+_FREE_PLANS: dict = {}
+_POOL_LIMIT = 1  # free plans kept per configuration
+
+
+def _take_plan(key, make):
+    free = _FREE_PLANS.get(key)
+    if free:
+        return free.pop()
+    return make()
+
+
+def _return_plan(key, plan):
+    free = _FREE_PLANS.setdefault(key, [])
+    if plan not in free and len(free) < _POOL_LIMIT:
+        free.append(plan)
+
+
+def release_cached_plans() -> None:
+    """Drop the adjoint plans kept for reuse by swept_heat and swept_ks (their
+    device memory is freed once no autograd graph refers to them)."""
+    _FREE_PLANS.clear()
+
+
+def _plan_for_backward(ctx, make, forward):
+    """The plan holding ctx's checkpoints, recomputing them when needed."""
+    plan = ctx.plan
+    if plan.generation != ctx.generation:
+        plan = _take_plan(ctx.key, make)
+        forward(plan)
+        ctx.plan, ctx.generation = plan, plan.generation
+    return plan
+
+
 def _swept_heat_fn():
     import torch
 
@@ -318,22 +372,29 @@ def _swept_heat_fn():
         dJ/du_0 and dJ/dalpha."""
 
         @staticmethod
-        def forward(ctx, u0, alpha, steps, dt, dx):
+        def forward(ctx, u0, alpha, steps, dt, dx, segment):
             u0 = u0.contiguous()
             alpha = alpha.contiguous()
-            plan = AdjointPlan(u0.shape[0], u0.shape[1], dt, dx, steps)
+            key = ("heat", u0.device.index, u0.shape[0], u0.shape[1], float(dt), float(dx), int(steps), segment)
+            ctx.make = lambda: AdjointPlan(u0.shape[0], u0.shape[1], dt, dx, steps, segment)
+            plan = _take_plan(key, ctx.make)
             uT = torch.empty_like(u0)
             plan.forward(u0, alpha, uT)
-            ctx.plan = plan
+            ctx.plan, ctx.key, ctx.generation = plan, key, plan.generation
+            ctx.save_for_backward(u0, alpha)
             return uT
 
         @staticmethod
         def backward(ctx, g_uT):
-            plan = ctx.plan
+            u0, alpha = ctx.saved_tensors
+            plan = _plan_for_backward(ctx, ctx.make, lambda p: p.forward(u0, alpha, torch.empty_like(u0)))
             g_u0 = torch.empty((plan.batch, plan.n), dtype=torch.float64, device=g_uT.device)
             g_alpha = torch.empty((plan.batch,), dtype=torch.float64, device=g_uT.device)
             plan.adjoint(g_uT.contiguous(), g_u0, g_alpha)
-            return g_u0, g_alpha, None, None, None
+            # a later forward may overwrite the checkpoints only after this
+            # reverse sweep has read them: it runs on the same stream
+            _return_plan(ctx.key, plan)
+            return g_u0, g_alpha, None, None, None, None
 
     return SweptHeatFn
 
@@ -341,12 +402,15 @@ def _swept_heat_fn():
 _SWEPT_HEAT_FN = None
 
 
-def swept_heat(u0, alpha, steps: int, dt: float, dx: float):
-    """Differentiable swept heat run: u0 [batch, n] float64, alpha [batch] float64."""
+def swept_heat(u0, alpha, steps: int, dt: float, dx: float, checkpoint_segment: int = 1):
+    """Differentiable swept heat run: u0 [batch, n] float64, alpha [batch] float64.
+    checkpoint_segment: 1 keeps every phase's edge state for the backward;
+    0 (two-level, about sqrt(phases) per segment) or k > 1 keep every k-th and
+    recompute the rest during the backward (less memory, one more forward)."""
     global _SWEPT_HEAT_FN
     if _SWEPT_HEAT_FN is None:
         _SWEPT_HEAT_FN = _swept_heat_fn()
-    return _SWEPT_HEAT_FN.apply(u0, alpha, int(steps), float(dt), float(dx))
+    return _SWEPT_HEAT_FN.apply(u0, alpha, int(steps), float(dt), float(dx), int(checkpoint_segment))
 
 
 def swept_ks_adjoint_create(batch: int, n: int, dtype, dt: float, dx: float, steps: int) -> ctypes.c_void_p:
@@ -386,6 +450,7 @@ class KsAdjointPlan:
         self.batch, self.n, self.steps = int(batch), int(n), int(steps)
         self._h = swept_ks_adjoint_create(batch, n, "f64", dt, dx, steps)
         self.info = swept_ks_adjoint_info(self._h)
+        self.generation = 0  # forward passes run so far (each rewrites the checkpoints)
 
     def _check(self, t, shape):
         import torch
@@ -398,6 +463,7 @@ class KsAdjointPlan:
         if u0.data_ptr() == uT.data_ptr():
             raise ValueError("u0 and uT may not alias")
         swept_ks_forward_ckpt(self._h, u0, uT, stream)
+        self.generation += 1
         return uT
 
     def adjoint(self, g_uT, g_u0, stream=None):
@@ -430,17 +496,22 @@ def _swept_ks_fn():
         @staticmethod
         def forward(ctx, u0, steps, dt, dx):
             u0 = u0.contiguous()
-            plan = KsAdjointPlan(u0.shape[0], u0.shape[1], dt, dx, steps)
+            key = ("ks", u0.device.index, u0.shape[0], u0.shape[1], float(dt), float(dx), int(steps))
+            ctx.make = lambda: KsAdjointPlan(u0.shape[0], u0.shape[1], dt, dx, steps)
+            plan = _take_plan(key, ctx.make)
             uT = torch.empty_like(u0)
             plan.forward(u0, uT)
-            ctx.plan = plan
+            ctx.plan, ctx.key, ctx.generation = plan, key, plan.generation
+            ctx.save_for_backward(u0)
             return uT
 
         @staticmethod
         def backward(ctx, g_uT):
-            plan = ctx.plan
+            (u0,) = ctx.saved_tensors
+            plan = _plan_for_backward(ctx, ctx.make, lambda p: p.forward(u0, torch.empty_like(u0)))
             g_u0 = torch.empty((plan.batch, plan.n), dtype=torch.float64, device=g_uT.device)
             plan.adjoint(g_uT.contiguous(), g_u0)
+            _return_plan(ctx.key, plan)
             return g_u0, None, None, None
 
     return SweptKsFn
@@ -521,5 +592,5 @@ __all__ = ["Plan", "SweptError", "swept_plan_create", "swept_run", "swept_run_no
            "swept_tile_geometry", "swept_autotune", "swept_autotune_lookup", "swept_autotune_forget",
            "Batch", "swept_batch_create", "swept_batch_run", "swept_batch_set_engine", "swept_batch_info",
            "swept_batch_destroy",
-           "AdjointPlan", "swept_heat", "swept_adjoint_create", "swept_forward_ckpt", "swept_adjoint_run",
-           "swept_adjoint_info", "swept_adjoint_destroy"]
+           "AdjointPlan", "swept_heat", "swept_adjoint_create", "swept_adjoint_create_segmented", "swept_forward_ckpt", "swept_adjoint_run",
+           "swept_adjoint_info", "swept_adjoint_destroy", "release_cached_plans"]

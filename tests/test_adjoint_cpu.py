@@ -52,3 +52,12 @@ def test_ks_adjoint_null_handles():
     assert lib.swept_ks_adjoint_run(None, None, None, None) == _lib.SWEPT_EINVAL
     assert lib.swept_ks_adjoint_info(None, None, None, None, None) == _lib.SWEPT_EINVAL
     lib.swept_ks_adjoint_destroy(None)
+
+
+def test_segmented_create_rejects_before_any_device_call():
+    import ctypes
+    h = ctypes.c_void_p()
+    lib = _lib.lib()
+    assert lib.swept_adjoint_create_segmented(ctypes.byref(h), 2, 256, 1, 1e-5, 1e-2, 100, -1) == _lib.SWEPT_EINVAL
+    assert lib.swept_adjoint_create_segmented(ctypes.byref(h), 0, 256, 1, 1e-5, 1e-2, 100, 0) == _lib.SWEPT_EINVAL
+    assert lib.swept_adjoint_create_segmented(None, 2, 256, 1, 1e-5, 1e-2, 100, 0) == _lib.SWEPT_EINVAL

@@ -115,3 +115,95 @@ def test_adjoint_full_size_central_differences():
         gd = float(np.dot(g_u0[b].cpu().numpy(), d))
         print(f"grid {b}: dJ/du0 . d swept {gd:.12e} central FD {fdu:.12e}")
         assert abs(fdu - gd) <= 1e-6 * max(abs(gd), 1e-12), (b, fdu, gd)
+
+
+def test_autograd_plans_are_reused_and_never_shared():
+    # two forwards awaiting their backwards hold two plans (no shared
+    # checkpoints); after a backward the plan goes back to the pool and the
+    # next forward of the same configuration takes it instead of allocating
+    from paper_1612_02495_amd import swept as sw
+    sw.release_cached_plans()
+    n, steps, batch = 128, 70, 2
+    dx = 1.0 / n
+    dt = dx * dx
+    rng = np.random.default_rng(11)
+    a = torch.tensor(rng.uniform(0.1, 0.4, size=batch), device="cuda", requires_grad=True)
+    ys = [torch.tensor(rng.standard_normal((batch, n)), device="cuda") for _ in range(2)]
+    xs = [torch.tensor(rng.standard_normal((batch, n)), device="cuda", requires_grad=True) for _ in range(2)]
+    Js = [0.5 * ((swept_heat(x, a, steps, dt, dx) - y) ** 2).sum() for x, y in zip(xs, ys)]
+    assert not sw._FREE_PLANS or not any(sw._FREE_PLANS.values())
+    for J in Js:
+        J.backward()
+    for x, y in zip(xs, ys):
+        for b in range(batch):
+            _, g, _ = oracle.heat_adjoint(x[b].detach().cpu().numpy(), y[b].cpu().numpy(), a[b].item(), dt, dx, steps)
+            assert np.array_equal(x.grad[b].cpu().numpy(), g)
+    pooled = [p for free in sw._FREE_PLANS.values() for p in free]
+    assert len(pooled) == 1
+    x = torch.tensor(rng.standard_normal((batch, n)), device="cuda", requires_grad=True)
+    J = 0.5 * ((swept_heat(x, a.detach(), steps, dt, dx) - ys[0]) ** 2).sum()
+    assert not any(sw._FREE_PLANS.values())  # the pooled plan was taken
+    J.backward()
+    assert [p for free in sw._FREE_PLANS.values() for p in free] == pooled
+    # a second backward of a graph whose plan has since run another forward
+    # recomputes its checkpoints (retain_graph): the same gradient
+    x1 = torch.tensor(rng.standard_normal((batch, n)), device="cuda", requires_grad=True)
+    J1 = 0.5 * ((swept_heat(x1, a.detach(), steps, dt, dx) - ys[0]) ** 2).sum()
+    J1.backward(retain_graph=True)
+    g_first = x1.grad.clone()
+    x2 = torch.tensor(rng.standard_normal((batch, n)), device="cuda", requires_grad=True)
+    J2 = 0.5 * ((swept_heat(x2, a.detach(), steps, dt, dx) - ys[1]) ** 2).sum()  # reuses J1's plan
+    x1.grad = None
+    J1.backward()
+    assert torch.equal(x1.grad, g_first)
+    J2.backward()
+    sw.release_cached_plans()
+
+
+@pytest.mark.parametrize("segment,steps", [(0, 32 * 40 + 7), (3, 32 * 10), (5, 32 * 11 + 31), (2, 64), (7, 40)])
+def test_two_level_checkpointing_gives_the_same_bits(segment, steps):
+    # keeping every segment-th phase's edge state and recomputing the others
+    # during the reverse sweep gives the gradients of the plan that keeps all
+    # (bit for bit, dJ/dalpha included), and those equal the oracle's
+    n, batch = 256, 2
+    dx = 1.0 / n
+    dt = dx * dx
+    rng = np.random.default_rng(segment * 1000 + steps)
+    alpha = rng.uniform(0.1, 0.4, size=batch)
+    u0 = rng.standard_normal((batch, n))
+    y = rng.standard_normal((batch, n))
+    outs = []
+    for seg in (1, segment):
+        plan = AdjointPlan(batch, n, dt, dx, steps, segment=seg)
+        du0 = torch.tensor(u0, device="cuda")
+        uT = torch.empty_like(du0)
+        plan.forward(du0, torch.tensor(alpha, device="cuda"), uT)
+        g = torch.empty_like(du0)
+        ga = torch.empty(batch, dtype=torch.float64, device="cuda")
+        plan.adjoint((uT - torch.tensor(y, device="cuda")).contiguous(), g, ga)
+        torch.cuda.synchronize()
+        outs.append((uT.cpu().numpy(), g.cpu().numpy(), ga.cpu().numpy(), plan.info["checkpoint_bytes"]))
+        plan.close()
+    (u1, g1, a1, b1), (u2, g2, a2, b2) = outs
+    assert np.array_equal(u1, u2) and np.array_equal(g1, g2) and np.array_equal(a1, a2)
+    K = steps // 32
+    if K > 2 and segment != 1:
+        assert b2 < b1
+    for b in range(batch):
+        _, gref, garef = oracle.heat_adjoint(u0[b], y[b], alpha[b], dt, dx, steps)
+        assert np.array_equal(g2[b], gref)
+        assert abs(a2[b] - garef) <= 1e-12 * abs(garef)
+
+
+def test_two_level_checkpoint_memory_of_the_gradient_workload():
+    # 64 grids of 2^18 points over 10^4 steps: 312 phases; segments of 18
+    # keep 18 + 17 sets instead of 312 (plan creation only, no run)
+    from paper_1612_02495_amd.swept import swept_adjoint_create_segmented, swept_adjoint_destroy, swept_adjoint_info
+    u0s, alpha, u0t, alpha_t, dt, dx, steps = inputs.heat_adjoint(batch=1)
+    n = u0s.shape[1]
+    h = swept_adjoint_create_segmented(64, n, "f64", dt, dx, steps, 0)
+    info = swept_adjoint_info(h)
+    swept_adjoint_destroy(h)
+    per_set = 64 * 2 * (n // 64) * 66 * 8
+    assert info["checkpoint_bytes"] == 35 * per_set
+    assert info["checkpoint_bytes"] <= 10e9

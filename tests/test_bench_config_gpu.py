@@ -50,3 +50,35 @@ def test_bench_workload_full_horizon_swept_equals_naive(name):
         bound = p.steps * p.n * np.finfo(np.float64).eps * np.abs(u0).max()
         assert abs(s.sum() - u0.sum()) <= bound
     plan.close()
+
+
+def test_ks_full_horizon_vs_oracle_at_2p16():
+    # KS at N = 2^16 over the workload's full 2*10^4 steps (t = 100, chaotic),
+    # autotuned configuration, against the FP64 oracle element by element.
+    # The oracle's all-cores leg gives the single-thread bits (pinned on the
+    # CPU) and finishes in seconds.
+    import oracle
+    p = inputs.ks(n=2 ** 16, steps=20000)
+    tuned = swept_autotune(p.n, "ks", "f64", p.dt, p.dx, p.alpha)
+    plan = Plan(p.n, "ks", torch.float64, p.dt, p.dx, tile_width=tuned["tile_width"],
+                steps_per_cycle=tuned["steps_per_cycle"], engine=tuned["engine"])
+    us = torch.tensor(p.u0, device="cuda")
+    plan.run(us, p.steps)
+    torch.cuda.synchronize()
+    ref, _ = oracle.ks_mt(p.u0, p.dt, p.dx, p.steps)
+    got = us.cpu().numpy()
+    assert np.array_equal(got, ref), f"rel max-norm {np.max(np.abs(got - ref)) / np.max(np.abs(ref))}"
+    plan.close()
+
+
+def test_ks_largest_grid_vs_oracle():
+    # the top of the KS size range, N = 2^22, at 1000 steps
+    import oracle
+    p = inputs.ks(n=2 ** 22, steps=1000)
+    plan = Plan(p.n, "ks", torch.float64, p.dt, p.dx, tile_width=1024)
+    us = torch.tensor(p.u0, device="cuda")
+    plan.run(us, p.steps)
+    torch.cuda.synchronize()
+    ref, _ = oracle.ks_mt(p.u0, p.dt, p.dx, p.steps)
+    assert np.array_equal(us.cpu().numpy(), ref)
+    plan.close()
