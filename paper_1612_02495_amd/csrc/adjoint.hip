@@ -22,6 +22,10 @@
 //      lambda slots, then its V part, handing the two outermost values of each
 //      gap tier on to the previous phase through the same slots;
 //   3. adds lambda(x,t) (u(x-1,t-1) + u(x+1,t-1) - 2u(x,t-1)) over its points.
+// The first phase (no V part) and the last (no Lambda part) run one region per
+// wave (region_kernel); every other phase runs the chained launch
+// (chain_kernel), where a wave keeps two regions of neighbouring tiles in
+// flight on complementary lanes.
 // The lambda slots mirror the forward edge slots: position-major [p][t & 1],
 // (h+1) positions per side, updated in place by the tile that owns them.
 // dJ/dalpha is summed per tile in phase order, then over tiles and remainder
@@ -29,7 +33,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "device_guard.h"
@@ -227,6 +233,369 @@ region_kernel(const double* __restrict__ ustart, const double* __restrict__ ck_i
     for (int s = kW / 2; s > 0; s >>= 1) acc = acc + __shfl_down(acc, s, kW);
     if (x == 0) partial[b * nt + j] += acc;
   }
+}
+
+// ------------------------------------------------------------------------
+// Chained reverse launch (every phase with both a V and a Lambda part).
+//
+// Within one region the V part widens tier by tier from the seam and the
+// Lambda part narrows towards the top, so a wave that walks one region at a
+// time leaves half of its lanes idle at every tier.  Here one wave walks a
+// chain of consecutive tiles of one grid and keeps two regions in flight:
+//   A_i: the forward recompute of the V part of tile i together with the
+//        Lambda part of tile i-1;
+//   B_i: the lambda walk of the Lambda part of tile i together with the V
+//        part of tile i-1.
+// Consecutive tiles of the chain use layouts rotated by 32 lanes against
+// each other (tile point q in lane q for even chain positions, in lane
+// (q + 32) mod 64 for odd ones), so a V part (centred on the seam, point 32)
+// and a Lambda part (centred on the tile middle) of neighbouring positions
+// fall on complementary lanes.  Lane shifts rotate across the wave, which
+// joins points 31 and 32 of a rotated tile; the tile ends (points 0 and 63)
+// take their outside neighbours from the tip registers as before.
+//
+// The Lambda part of A_i runs two tiers behind the V part's mirror tier
+// (Lambda tier h+s+2 beside V tier s), and likewise in B_i (Lambda tier
+// h+d+2 beside V tier d).  The four lanes that then belong to neither part
+// are exactly those that hold the band values (A) or the injected lambda
+// values of later regions (B), so each lane either computes a point of one
+// of the two regions or holds an input of the next tier.
+//
+// For heat, lambda does not depend on u, so the two history sets a tile needs
+// are made in either order: the lambda walk of tile i's Lambda part (B_i)
+// keeps lambda per tier, the recompute of that part (A_{i+1}) pairs it with
+// the Laplacian as it forms; the recompute of tile i's V part (A_i) keeps the
+// Laplacian per tier, the lambda walk of that part (B_{i+1}) pairs it with
+// lambda as it forms.  Register set Z[t] of one chain parity holds the V
+// Laplacian of tier t on the V lanes and the Lambda lambda of tier h+t on
+// the others; a slot is rewritten only two tiers after its last read.  The
+// lambda values, the hand-off values and the edge slots are those of the
+// one-region kernel bit for bit; the dJ/dalpha terms are the same products,
+// summed per tile in another (fixed) order.
+constexpr int kDppWaveRor1 = 0x13C;  // lane i <- lane i-1, lane 0 <- lane 63
+constexpr int kDppWaveRol1 = 0x134;  // lane i <- lane i+1, lane 63 <- lane 0
+
+// Lane mask of a set of tile points (bit q = point q) in layout L.
+template <int L>
+__host__ __device__ constexpr uint64_t lmask(uint64_t pts) {
+  return L ? (pts << 32) | (pts >> 32) : pts;
+}
+// The lane of tile point q, and the point held by lane x, in layout L (the
+// rotation by 32 is its own inverse).
+template <int L>
+__host__ __device__ constexpr int rot_lane(int q) {
+  return L ? (q + 32) & 63 : q;
+}
+
+// Calls f(integral_constant<int, I>) for I = B, B+S, ... up to and including
+// E, so that every step of a walk sees its tier as a constant expression.
+template <int B, int E, int S, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr ((S > 0 && B <= E) || (S < 0 && B >= E)) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + S, E, S>(f);
+  }
+}
+
+// Lane masks of the chained walks, by layout L, step and use: a constant
+// table read with scalar loads.  (A 64-bit mask has no literal form; formed
+// from immediates in the loop, or kept in scalar registers across it, the
+// masks cost more issue slots than the selects they drive.)
+enum ChainMask { kCmBand, kCmAccA, kCmTipA0, kCmTipA1, kCmAccB, kCmHand, kCmInj, kCmTipB0, kCmTipB1, kCmKinds };
+constexpr int kCmSteps = kH + 3;  // steps s = -1 .. h of A and d = h .. -1 of B
+struct ChainMasks {
+  uint64_t m[2][kCmSteps][kCmKinds];
+};
+
+__host__ __device__ constexpr uint64_t lmask_rt(int L, uint64_t pts) { return L ? (pts << 32) | (pts >> 32) : pts; }
+__host__ __device__ constexpr int rot_lane_rt(int L, int q) { return L ? (q + 32) & 63 : q; }
+
+constexpr ChainMasks make_chain_masks() {
+  ChainMasks t{};
+  for (int L = 0; L < 2; ++L) {
+    for (int s = -1; s <= kH; ++s) {  // A: V tier s (layout L), Lambda tier h+s+2 (layout 1-L)
+      uint64_t* e = t.m[L][s + 1];
+      const int m = s + 2;
+      e[kCmBand] = s >= 1 ? lmask_rt(L, pair_bits(kA - s - 1) | pair_bits(kA + s - 1)) : 0;
+      e[kCmAccA] = m >= 1 && m <= kH - 1 ? lmask_rt(1 - L, wave::range_bits(m, kW - m)) : 0;
+      e[kCmTipA0] = s == kH ? 1ull << rot_lane_rt(L, 0) : 0;
+      e[kCmTipA1] = s == kH ? 1ull << rot_lane_rt(L, kW - 1) : 0;
+    }
+    for (int d = kH; d >= -1; --d) {  // B: V tier d (layout 1-L), Lambda tier h+d+2 (layout L)
+      uint64_t* e = t.m[L][kH - d];
+      const int m = d + 2;
+      e[kCmAccB] = d >= 1 ? lmask_rt(1 - L, wave::range_bits(kA - d, kA + d)) : 0;
+      e[kCmHand] = d >= 1 ? lmask_rt(1 - L, pair_bits(kA - d) | pair_bits(kA + d - 2)) : 0;
+      e[kCmInj] = m >= 1 && m <= kH ? lmask_rt(L, pair_bits(m - 2) | pair_bits(kW - m)) : 0;
+      e[kCmTipB0] = d == kH ? 1ull << rot_lane_rt(1 - L, 0) : 0;
+      e[kCmTipB1] = d == kH ? 1ull << rot_lane_rt(1 - L, kW - 1) : 0;
+    }
+  }
+  return t;
+}
+__constant__ ChainMasks kChainMasks = make_chain_masks();
+typedef const __attribute__((address_space(4))) uint64_t* MaskPtr;
+
+// dst = v on the lanes of m (a per-lane select).
+__device__ __forceinline__ void set_on(uint64_t m, double v, double& dst) { dst = wave::pick(wave::lanes(m), v, dst); }
+
+// acc = fma(a, b, acc) on the lanes of m, under an execution mask: one
+// operation instead of a multiply-add and a select.  The empty asm statement
+// cannot be speculated, so the block is not turned into a select; free of
+// side effects, it lets the scheduler move loads across it.
+__device__ __forceinline__ void fma_on(uint64_t m, double a, double b, double& acc) {
+  if (wave::lanes(m)) {
+    acc = __builtin_fma(a, b, acc);
+    asm("" : "+v"(acc));
+  }
+}
+
+// History writes in place: the new value takes the register of the slot's
+// previous value (dead by then), which the register allocator does not find
+// by itself across the chain loop.  Same operations and rounding as
+// fma(-2, row, sum) and a + b.
+__device__ __forceinline__ void lap_into(double& z, double row, double sum) {
+  asm("v_fma_f64 %0, -2.0, %1, %2" : "+v"(z) : "v"(row), "v"(sum));
+}
+__device__ __forceinline__ void add_into(double& z, double a, double b) {
+  asm("v_add_f64 %0, %1, %2" : "+v"(z) : "v"(a), "v"(b));
+}
+
+// Chain position i (layout L = i mod 2): A_i then B_i, then the hand-off
+// stores and the dJ/dalpha partial of tile i-1.  ZA is the register set of
+// parity i, ZB that of parity i+1.
+// Offsets of the slot entries that the lane holding tile point q of tile j
+// reads: its band (or lambda) pair, and the outside neighbour of a tile end
+// (point -1 for point 0, point w for point w-1; position 0 of the left slot,
+// position w-a = h of the right one, odd tier parity).
+__device__ __forceinline__ void tile_src(int64_t base, int64_t nt, int par, int64_t j, int q, int64_t& src,
+                                         int64_t& tsrc) {
+  const int64_t sL = base + (par ? (nt + j) * kSL : j * kSL);
+  const int64_t sR = base + (par ? (j + 1 == nt ? 0 : j + 1) * kSL : (nt + j) * kSL);
+  src = q < kA ? sL + 2 * (q + 1) : sR + 2 * (q - kA);
+  tsrc = q == 0 ? sL + ((kH - 1) & 1) : sR + 2 * (kW - kA) + ((kH - 1) & 1);
+}
+
+// One tile's inputs staged in LDS by direct loads from global memory, a chain
+// position ahead of their use, so that their latency is hidden without
+// holding registers: per lane (layout of the tile), the band pair and the
+// lambda pair of its point, and the slot position that holds the outside
+// neighbour of a tile end (its odd-parity entry is the tip).
+struct ChainStage {
+  double band[kW][2];
+  double lam[kW][2];
+  double tip[kW][2];
+  double ltip[kW][2];
+};
+typedef __attribute__((address_space(3))) void* LdsPtr;
+constexpr int kWaitVmcnt0 = 0x0F70;  // s_waitcnt vmcnt(0), other counters not waited on
+
+template <int L>
+__device__ __forceinline__ void stage_tile(const double* ck_in, const double* lam_slots, int64_t base, int64_t nt,
+                                           int par, int64_t j, int x, ChainStage& st) {
+  int64_t src, tsrc;
+  tile_src(base, nt, par, j, rot_lane<L>(x), src, tsrc);
+  // lane x's 16 bytes land at byte 16x of the destination (tsrc is the odd
+  // entry of its position: the pair starts one entry before)
+  __builtin_amdgcn_global_load_lds(ck_in + src, (LdsPtr)&st.band[0][0], 16, 0, 0);
+  __builtin_amdgcn_global_load_lds(lam_slots + src, (LdsPtr)&st.lam[0][0], 16, 0, 0);
+  __builtin_amdgcn_global_load_lds(ck_in + tsrc - 1, (LdsPtr)&st.tip[0][0], 16, 0, 0);
+  __builtin_amdgcn_global_load_lds(lam_slots + tsrc - 1, (LdsPtr)&st.ltip[0][0], 16, 0, 0);
+}
+
+// The outputs of tile j (layout L): the lambda values handed to the previous
+// phase (o0, o1: by tier parity) and its running dJ/dalpha sum (lane 0).
+// Left side p = q: points q <= a at d = a-q, a-q+1; right side p = q-a+1:
+// points q >= a-1 at d = q-a+1, q-a+2 (d in [1, h]).
+template <int L>
+__device__ __forceinline__ void store_outputs(double* lam_slots, double* __restrict__ partial, int64_t base,
+                                              int64_t nt, int par, int64_t b, int64_t j, int x, double o0, double o1,
+                                              double sum) {
+  const int64_t sL = base + (par ? (nt + j) * kSL : j * kSL);
+  const int64_t sR = base + (par ? (j + 1 == nt ? 0 : j + 1) * kSL : (nt + j) * kSL);
+  const int q = rot_lane<L>(x);
+  if (q <= kA) {
+    double* const out = lam_slots + sL + 2 * q;
+    const int d0 = kA - q, d1 = kA - q + 1;
+    if (d0 >= 1) out[d0 & 1] = (d0 & 1) ? o1 : o0;
+    if (d1 <= kH) out[d1 & 1] = (d1 & 1) ? o1 : o0;
+  }
+  if (q >= kA - 1) {
+    double* const out = lam_slots + sR + 2 * (q - kA + 1);
+    const int d0 = q - kA + 1, d1 = q - kA + 2;
+    if (d0 >= 1) out[d0 & 1] = (d0 & 1) ? o1 : o0;
+    if (d1 <= kH) out[d1 & 1] = (d1 & 1) ? o1 : o0;
+  }
+  if (x == 0) partial[b * nt + j] = sum;
+}
+
+template <int L>
+__device__ __forceinline__ void chain_position(const double* __restrict__ ck_in, double* lam_slots,
+                                               double* __restrict__ partial, const Consts<double>& k, int64_t b,
+                                               int64_t nt, int par, int64_t j0, int64_t i, int64_t count, double& row,
+                                               double& lam, double& ltp, double (&ZA)[kH + 1],
+                                               double (&ZB)[kH + 1], ChainStage (&stage)[2], double& po0,
+                                               double& po1, double& psum) {
+  using wave::dpp_move0;
+  // the lane index, opaque to the compiler in each position: lane-dependent
+  // offsets are then formed where they are used instead of being kept (and
+  // spilled) across the chain loop
+  int x = threadIdx.x;
+  asm volatile("" : "+v"(x));
+  const int64_t base = b * 2 * nt * kSL;
+  // the mask table of layout L; the empty asm statement keeps its loads in the
+  // chain loop
+  MaskPtr mt = (MaskPtr)(&kChainMasks.m[L][0][0]);
+  asm volatile("" : "+s"(mt));
+  // inputs of tile i from its stage (for i = count the stage holds the
+  // finite inputs of an earlier tile, which only reach lanes whose results are
+  // not kept): band values and tips of its V part here, lambda of later
+  // regions beside its Lambda part and beyond its ends at the start of B_i;
+  // then the inputs of tile i+1 are staged
+  // (the stage was filled a position ago; waiting for every vector memory
+  // operation here also covers the outputs stored at the start of that
+  // position, long complete)
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  const double bv0 = stage[L].band[x][0], bv1 = stage[L].band[x][1], tip = stage[L].tip[x][1];
+  if (i + 1 < count) stage_tile<1 - L>(ck_in, lam_slots, base, nt, par, j0 + i + 1, x, stage[1 - L]);
+  // outputs of tile i-2 (same layout), kept from the end of the last position
+  if (i >= 2) store_outputs<L>(lam_slots, partial, base, nt, par, b, j0 + i - 2, x, po0, po1, psum);
+
+  // ---- A_i: V tier s of tile i (layout L) beside Lambda tier h+s+2 of tile
+  // i-1 (layout 1-L)
+  double acc = 0.0;
+  // masks of step index k are loaded two steps ahead of their use
+  uint64_t ma[kCmSteps][2];
+  static_for<0, 1, 1>([&](auto kc) {
+    constexpr int kk = decltype(kc)::value;
+    ma[kk][0] = mt[kk * kCmKinds + kCmBand];
+    ma[kk][1] = mt[kk * kCmKinds + kCmAccA];
+  });
+  static_for<-1, kH, 1>([&](auto sc) {
+    constexpr int s = decltype(sc)::value;
+    if constexpr (s + 3 < kCmSteps) {
+      ma[s + 3][0] = mt[(s + 3) * kCmKinds + kCmBand];
+      ma[s + 3][1] = mt[(s + 3) * kCmKinds + kCmAccA];
+    }
+    if constexpr (s >= 1)  // band of tier s-1: [a-s-1, a-s+1) and [a+s-1, a+s+1)
+      set_on(ma[s + 1][0], ((s - 1) & 1) ? bv1 : bv0, row);
+    double lo = dpp_move0<kDppWaveRor1>(row), hi = dpp_move0<kDppWaveRol1>(row);
+    if constexpr (s == kH) {
+      set_on(mt[(s + 1) * kCmKinds + kCmTipA0], tip, lo);
+      set_on(mt[(s + 1) * kCmKinds + kCmTipA1], tip, hi);
+    }
+    const double sum = hi + lo;
+    double lap;
+    if constexpr (s >= 1) {
+      lap_into(ZA[s], row, sum);
+      lap = ZA[s];
+    } else {
+      lap = __builtin_fma(-2.0, row, sum);
+    }
+    constexpr int m = s + 2;
+    if constexpr (m >= 1 && m <= kH - 1)  // Lambda tier h+m of tile i-1: [m, w-m)
+      fma_on(ma[s + 1][1], ZA[m], lap, acc);
+    row = k.fo * sum + k.c * row;  // heat_update(lo, row, hi)
+  });
+
+  // ---- B_i: Lambda tier h+d+2 of tile i (layout L) beside V tier d of tile
+  // i-1 (layout 1-L), d = h .. -1
+  const double in0 = stage[L].lam[x][0], in1 = stage[L].lam[x][1], ltn = stage[L].ltip[x][1];
+  // the running dJ/dalpha sum of tile i-1, a walk ahead of its update
+  double part = 0.0;
+  if (i >= 1 && x == 0) part = partial[b * nt + j0 + i - 1];
+  double o0 = 0.0, o1 = 0.0;
+  uint64_t mb[kCmSteps][3];
+  static_for<0, 1, 1>([&](auto kc) {
+    constexpr int kk = decltype(kc)::value;
+    mb[kk][0] = mt[kk * kCmKinds + kCmAccB];
+    mb[kk][1] = mt[kk * kCmKinds + kCmHand];
+    mb[kk][2] = mt[kk * kCmKinds + kCmInj];
+  });
+  static_for<kH, -1, -1>([&](auto dc) {
+    constexpr int d = decltype(dc)::value;
+    if constexpr (kH - d + 2 < kCmSteps) {
+      mb[kH - d + 2][0] = mt[(kH - d + 2) * kCmKinds + kCmAccB];
+      mb[kH - d + 2][1] = mt[(kH - d + 2) * kCmKinds + kCmHand];
+      mb[kH - d + 2][2] = mt[(kH - d + 2) * kCmKinds + kCmInj];
+    }
+    double lo = dpp_move0<kDppWaveRor1>(lam), hi = dpp_move0<kDppWaveRol1>(lam);
+    if constexpr (d == kH) {
+      set_on(mt[(kH - d) * kCmKinds + kCmTipB0], ltp, lo);
+      set_on(mt[(kH - d) * kCmKinds + kCmTipB1], ltp, hi);
+    }
+    constexpr int m = d + 2;
+    // heat_update(lo, lam, hi); Lambda tier h+m of tile i is kept for A_{i+1}
+    const double t0 = k.fo * (hi + lo), t1 = k.c * lam;
+    if constexpr (m >= 1 && m <= kH - 1) {
+      add_into(ZB[m], t0, t1);
+      lam = ZB[m];
+    } else {
+      lam = t0 + t1;
+    }
+    if constexpr (d >= 1) {
+      // dJ/dalpha term of V tier d of tile i-1, gap [a-d, a+d)
+      fma_on(mb[kH - d][0], lam, ZB[d], acc);
+      // the two outermost values on each side of the gap go to the previous
+      // phase (one register per tier parity, as in the one-region kernel)
+      const uint64_t hand = mb[kH - d][1];
+      if constexpr (d & 1)
+        set_on(hand, lam, o1);
+      else
+        set_on(hand, lam, o0);
+      asm("" : "+v"(o0), "+v"(o1));
+    }
+    if constexpr (m >= 1 && m <= kH)  // lambda of later regions just outside Lambda tier h+m
+      set_on(mb[kH - d][2], (m & 1) ? in1 : in0, lam);
+  });
+
+
+  if (i >= 1) {
+    // outputs of tile i-1, stored at the start of the next position
+#pragma unroll
+    for (int s = kW / 2; s > 0; s >>= 1) acc = acc + __shfl_down(acc, s, kW);
+    po0 = o0;
+    po1 = o1;
+    psum = part + acc;
+  }
+  ltp = ltn;
+}
+
+// The chained reverse launch of one middle phase: workgroup (c, b) walks
+// tiles c*chain .. c*chain+chain-1 of grid b (fewer at the end of the grid).
+// Measured on 64 grids of 2^18 points: chains of 8, 16 and 32 tiles take
+// 0.458, 0.439 and 0.443 ms per launch (the first and last position of a
+// chain carry one region each; long chains leave the last round of
+// workgroups part-empty).
+constexpr int kChain = 16;
+__global__ void __launch_bounds__(kW) __attribute__((amdgpu_waves_per_eu(3)))
+chain_kernel(const double* __restrict__ ck_in, double* lam_slots, double* __restrict__ partial,
+             const Consts<double>* __restrict__ kb, int64_t nt, int p, int chain) {
+  const int64_t b = blockIdx.y;
+  const int64_t j0 = (int64_t)blockIdx.x * chain;
+  const int64_t count = nt - j0 < chain ? nt - j0 : chain;
+  const Consts<double> k = kb[b];
+  const int par = p & 1;
+  double Z0[kH + 1], Z1[kH + 1];
+#pragma unroll
+  for (int u = 0; u <= kH; ++u) Z0[u] = Z1[u] = 0.0;
+  __shared__ ChainStage stage[2];
+  const int64_t base = b * 2 * nt * kSL;
+  stage_tile<0>(ck_in, lam_slots, base, nt, par, j0, threadIdx.x, stage[0]);
+  double row = 0.0, lam = 0.0, ltp = 0.0, po0 = 0.0, po1 = 0.0, psum = 0.0;
+  for (int64_t i = 0; i <= count; i += 2) {
+    chain_position<0>(ck_in, lam_slots, partial, k, b, nt, par, j0, i, count, row, lam, ltp, Z0, Z1, stage, po0,
+                          po1, psum);
+    if (i + 1 > count) break;
+    chain_position<1>(ck_in, lam_slots, partial, k, b, nt, par, j0, i + 1, count, row, lam, ltp, Z1, Z0, stage,
+                          po0, po1, psum);
+  }
+  // the outputs of the last tile of the chain
+  const int64_t jl = j0 + count - 1;
+  if ((count - 1) & 1)
+    store_outputs<1>(lam_slots, partial, base, nt, par, b, jl, threadIdx.x, po0, po1, psum);
+  else
+    store_outputs<0>(lam_slots, partial, base, nt, par, b, jl, threadIdx.x, po0, po1, psum);
 }
 
 // Lane mask of register r when each lane holds P consecutive tile points and
@@ -677,10 +1046,16 @@ int swept_adjoint_run(swept_adjoint a, const void* g_uT, void* g_u0, double* g_a
         if (e != hipSuccess) break;
       }
       const double* ck_in = p > 0 ? ckpt_set(a, p - 1) : nullptr;
-      auto kern = p == 0 ? swept::adj::region_kernel<false, true>
-                  : (p == a->K ? swept::adj::region_kernel<true, false> : swept::adj::region_kernel<true, true>);
-      hipLaunchKernelGGL(kern, dim3((unsigned)a->nt, (unsigned)a->batch), dim3(kW), 0, st, ur, ck_in,
-                         static_cast<const double*>(g_uT), a->lam_slots, lam_r, a->tiles, k, a->n, a->nt, p);
+      if (p > 0 && p < a->K) {
+        constexpr int ch = swept::adj::kChain;
+        hipLaunchKernelGGL(swept::adj::chain_kernel, dim3((unsigned)((a->nt + ch - 1) / ch), (unsigned)a->batch),
+                           dim3(kW), 0, st, ck_in, a->lam_slots, a->tiles, k, a->nt, p, ch);
+      } else {
+        // the first phase (no V part) and the last (no Lambda part)
+        auto kern = p == 0 ? swept::adj::region_kernel<false, true> : swept::adj::region_kernel<true, false>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)a->nt, (unsigned)a->batch), dim3(kW), 0, st, ur, ck_in,
+                           static_cast<const double*>(g_uT), a->lam_slots, lam_r, a->tiles, k, a->n, a->nt, p);
+      }
       e = hipGetLastError();
     }
   }

@@ -14,8 +14,11 @@ pytestmark = pytest.mark.gpu
 
 
 # n = 576 is 9 tiles: the 8-tile waves of the checkpointing forward end in a
-# wave holding one tile
-@pytest.mark.parametrize("n,steps", [(64, 5), (64, 32), (128, 45), (256, 96), (192, 101), (512, 333), (576, 70)])
+# wave holding one tile; n = 2112 (33 tiles) and 2560 (40 tiles) give the
+# chained reverse launch (chains of 16 tiles) two full chains and a last
+# chain of 1 and of 8 tiles, with chains of odd and even length
+@pytest.mark.parametrize("n,steps", [(64, 5), (64, 32), (128, 45), (256, 96), (192, 101), (512, 333), (576, 70),
+                                     (2112, 130), (2560, 97)])
 def test_adjoint_matches_cpu_reverse_sweep(n, steps):
     rng = np.random.default_rng(n * 1000 + steps)
     batch = 3
