@@ -24,16 +24,18 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nt) {
 // the ring seam: at the middle of the last tile of the shifted tiling
 // (parity 1), or at the first point of tile 0 and the last of tile nt-1
 // (parity 0).  Only those tiles run the tier code with the mirror ghosts.
-template <int KIND, typename T, int P, int ROLE, bool INS>
+// POISON: fill the tile's LDS with NaN first (a separate instantiation, so
+// that the production kernel carries no branch for it).
+template <int KIND, typename T, int P, int ROLE, bool INS, bool POISON>
 __global__ void __launch_bounds__(64)
-phase_compact_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, int hl, Consts<T> k, int poison) {
+phase_compact_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, int hl, Consts<T> k) {
   constexpr int S = Radius<KIND>::value;
   constexpr int W = 64 * P;
   constexpr int HALF = 32 * P;
   constexpr int SLEN = W + 2 * S;
   __shared__ T sb[compact::Lds<KIND, P>::band];
   __shared__ T stg[compact::Lds<KIND, P>::stage];
-  if (poison) {
+  if constexpr (POISON) {
     poison_lds(sb, compact::Lds<KIND, P>::band, (int)threadIdx.x, 64);
     poison_lds(stg, compact::Lds<KIND, P>::stage, (int)threadIdx.x, 64);
     compact::wave_sync();
@@ -55,13 +57,19 @@ phase_compact_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, 
   compact::tile_phase<KIND, T, P, ROLE>(u, n, origin, sL, sR, hv, hl, k, (int)threadIdx.x, sb, stg);
 }
 
+template <int KIND, typename T, int P, bool INS, bool POISON>
+hipError_t launch_pp(const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
+  auto kern = a.hv == 0 ? phase_compact_kernel<KIND, T, P, 0, INS, POISON>
+              : (a.hl == 0 ? phase_compact_kernel<KIND, T, P, 2, INS, POISON>
+                           : phase_compact_kernel<KIND, T, P, 1, INS, POISON>);
+  hipLaunchKernelGGL(kern, dim3((unsigned)a.nt), dim3(64), 0, st, static_cast<T*>(a.u), static_cast<T*>(a.slots),
+                     a.n, a.nt, a.parity, a.hv, a.hl, k);
+  return hipGetLastError();
+}
+
 template <int KIND, typename T, int P, bool INS>
 hipError_t launch_p(const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
-  auto kern = a.hv == 0 ? phase_compact_kernel<KIND, T, P, 0, INS>
-              : (a.hl == 0 ? phase_compact_kernel<KIND, T, P, 2, INS> : phase_compact_kernel<KIND, T, P, 1, INS>);
-  hipLaunchKernelGGL(kern, dim3((unsigned)a.nt), dim3(64), 0, st, static_cast<T*>(a.u), static_cast<T*>(a.slots),
-                     a.n, a.nt, a.parity, a.hv, a.hl, k, a.poison);
-  return hipGetLastError();
+  return a.poison ? launch_pp<KIND, T, P, INS, true>(a, k, st) : launch_pp<KIND, T, P, INS, false>(a, k, st);
 }
 
 }  // namespace

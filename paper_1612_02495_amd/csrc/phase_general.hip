@@ -16,14 +16,15 @@
 namespace swept {
 namespace {
 
-template <int KIND, typename T, int P>
+// POISON: fill the tile's LDS with NaN first (a separate instantiation).
+template <int KIND, typename T, int P, bool POISON>
 __global__ void __launch_bounds__(64)
-phase_general_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, int hl, Consts<T> k, int poison) {
+phase_general_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, int hl, Consts<T> k) {
   constexpr int S = Radius<KIND>::value;
   constexpr int SLEN = 64 * P + 2 * S;
   __shared__ T sb[compact::Lds<KIND, P>::band];
   __shared__ T stg[compact::Lds<KIND, P>::stage];
-  if (poison) {
+  if constexpr (POISON) {
     poison_lds(sb, compact::Lds<KIND, P>::band, (int)threadIdx.x, 64);
     poison_lds(stg, compact::Lds<KIND, P>::stage, (int)threadIdx.x, 64);
     compact::wave_sync();
@@ -40,8 +41,9 @@ phase_general_kernel(T* u, T* slots, int64_t n, int64_t nt, int parity, int hv, 
 
 template <int KIND, typename T, int P>
 hipError_t launch_p(const PhaseArgs& a, const Consts<T>& k, hipStream_t st) {
-  hipLaunchKernelGGL((phase_general_kernel<KIND, T, P>), dim3((unsigned)a.nt), dim3(64), 0, st,
-                     static_cast<T*>(a.u), static_cast<T*>(a.slots), a.n, a.nt, a.parity, a.hv, a.hl, k, a.poison);
+  auto kern = a.poison ? phase_general_kernel<KIND, T, P, true> : phase_general_kernel<KIND, T, P, false>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)a.nt), dim3(64), 0, st, static_cast<T*>(a.u), static_cast<T*>(a.slots),
+                     a.n, a.nt, a.parity, a.hv, a.hl, k);
   return hipGetLastError();
 }
 
