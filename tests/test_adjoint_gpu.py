@@ -112,12 +112,15 @@ def test_adjoint_full_size_central_differences():
         ga = g_a[b].item()
         print(f"grid {b}: dJ/dalpha swept {ga:.12e} central FD {fd:.12e} rel {abs(fd - ga) / abs(ga):.2e}")
         assert abs(fd - ga) <= 1e-6 * abs(ga), (b, fd, ga)
-        d = rng.standard_normal(n)
-        d /= np.linalg.norm(d)
-        fdu = (J(b, u0s[b] + hu * d, alpha[b]) - J(b, u0s[b] - hu * d, alpha[b])) / (2 * hu)
-        gd = float(np.dot(g_u0[b].cpu().numpy(), d))
-        print(f"grid {b}: dJ/du0 . d swept {gd:.12e} central FD {fdu:.12e}")
-        assert abs(fdu - gd) <= 1e-6 * max(abs(gd), 1e-12), (b, fdu, gd)
+        # eight random unit directions per grid
+        g = g_u0[b].cpu().numpy()
+        for k in range(8):
+            d = rng.standard_normal(n)
+            d /= np.linalg.norm(d)
+            fdu = (J(b, u0s[b] + hu * d, alpha[b]) - J(b, u0s[b] - hu * d, alpha[b])) / (2 * hu)
+            gd = float(np.dot(g, d))
+            print(f"grid {b} direction {k}: dJ/du0 . d swept {gd:.12e} central FD {fdu:.12e}")
+            assert abs(fdu - gd) <= 1e-6 * max(abs(gd), 1e-12), (b, k, fdu, gd)
 
 
 def test_autograd_plans_are_reused_and_never_shared():
