@@ -406,7 +406,12 @@ __device__ __forceinline__ void stage_tile(const double* ck_in, const double* la
 // The outputs of tile j (layout L): the lambda values handed to the previous
 // phase (o0, o1: by tier parity) and its running dJ/dalpha sum (lane 0).
 // Left side p = q: points q <= a at d = a-q, a-q+1; right side p = q-a+1:
-// points q >= a-1 at d = q-a+1, q-a+2 (d in [1, h]).
+// points q >= a-1 at d = q-a+1, q-a+2 (d in [1, h]).  The two tiers of a
+// lane differ in parity, so a lane with both in range fills both entries of
+// its position, [p][0] = o0 and [p][1] = o1, with one 16-byte store: points
+// 1 .. a-1 on the left, a .. w-2 on the right.  The four others have one
+// tier each: point 0 left [0][0] and point w-1 right [h][0] (o0), point a-1
+// right [0][1] and point a left [h][1] (o1).
 template <int L>
 __device__ __forceinline__ void store_outputs(double* lam_slots, double* __restrict__ partial, int64_t base,
                                               int64_t nt, int par, int64_t b, int64_t j, int x, double o0, double o1,
@@ -414,17 +419,13 @@ __device__ __forceinline__ void store_outputs(double* lam_slots, double* __restr
   const int64_t sL = base + (par ? (nt + j) * kSL : j * kSL);
   const int64_t sR = base + (par ? (j + 1 == nt ? 0 : j + 1) * kSL : (nt + j) * kSL);
   const int q = rot_lane<L>(x);
-  if (q <= kA) {
-    double* const out = lam_slots + sL + 2 * q;
-    const int d0 = kA - q, d1 = kA - q + 1;
-    if (d0 >= 1) out[d0 & 1] = (d0 & 1) ? o1 : o0;
-    if (d1 <= kH) out[d1 & 1] = (d1 & 1) ? o1 : o0;
+  if (q >= 1 && q <= kW - 2) {
+    double* const pos = lam_slots + (q < kA ? sL + 2 * q : sR + 2 * (q - kA + 1));
+    *reinterpret_cast<double2*>(pos) = make_double2(o0, o1);
   }
-  if (q >= kA - 1) {
-    double* const out = lam_slots + sR + 2 * (q - kA + 1);
-    const int d0 = q - kA + 1, d1 = q - kA + 2;
-    if (d0 >= 1) out[d0 & 1] = (d0 & 1) ? o1 : o0;
-    if (d1 <= kH) out[d1 & 1] = (d1 & 1) ? o1 : o0;
+  if (q == 0 || q == kA - 1 || q == kA || q == kW - 1) {
+    double* const e = lam_slots + (q == 0 ? sL : (q == kA - 1 ? sR + 1 : (q == kA ? sL + 2 * kA + 1 : sR + 2 * kH)));
+    *e = (q == 0 || q == kW - 1) ? o0 : o1;
   }
   if (x == 0) partial[b * nt + j] = sum;
 }
