@@ -34,17 +34,20 @@ if ROOT not in sys.path:
 METRIC = "cell-updates/sec, swept vs naive on 1 GPU (FP64 heat/KS); adjoint grad time"
 
 # Algorithmic cost per cell update of one tier (IEEE adds/subtracts/multiplies
-# in stencil.h; negation is a free source modifier):
-#   heat: Fo*(r + l) + c*o                        -> 4
-#   KS:   rhs 18 + (u + h*rhs) 2, per sub-step    -> 20  (two sub-steps per step)
+# in stencil.h, a fused multiply-add counting as two; negation is a free
+# source modifier), and the floating-point instructions that carry it:
+#   heat: fma(Fo, r + l, c*o)                     -> 4 flops in 3 instructions
+#   KS:   rhs 18 in 14 + fma(h, rhs, u) 2 in 1    -> 20 in 15  (two sub-steps per step)
 FLOPS_PER_TIER_UPDATE = {"heat": 4, "heat_insulated": 4, "ks": 20}
+FP_INSTR_PER_TIER_UPDATE = {"heat": 3, "heat_insulated": 3, "ks": 15}
 TIERS_PER_STEP = {"heat": 1, "heat_insulated": 1, "ks": 2}
 # MI355X's published dense vector peaks (an FMA counts as two operations).
 PUBLISHED_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
-# Add/mul issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one operation
-# per lane per clock.  The bit-exact operation order has no FMA (contraction
-# off) and packed FP32 is disabled, so this is what the stencil code can reach.
-ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Vector instruction issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
+# lane-instruction per lane per clock (packed FP32 is disabled).  A kernel
+# whose operation order carries f flops in i instructions can reach at most
+# this rate times f / i.
+ALU_ISSUE_TERA = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBPS = 8000.0
 
 WORKLOADS = {
@@ -77,17 +80,20 @@ NESTED = ["ks", "batch", "batch_ks", "adjoint", "ks_adjoint"]
 DATA = "synthetic (seeded; see paper_1612_02495_amd/inputs.py)"
 
 
-def roofline(kernel, flops, t_launch, dtype, traffic=None):
-    """ALU roofline of one kernel launch: algorithmic flops / launch time."""
+def roofline(kernel, flops, t_launch, dtype, traffic=None, fp_instr=None):
+    """ALU roofline of one kernel launch: algorithmic flops / launch time.
+    fp_instr: the floating-point instructions (lane-instructions) that carry
+    those flops in the kernel's operation order; sets the issue-rate ceiling."""
     achieved = flops / t_launch / 1e12
     peak = PUBLISHED_PEAK_TFLOPS[dtype]
+    issue = ALU_ISSUE_TERA * flops / (fp_instr if fp_instr else flops)
     return {"bound": "alu", "kernel": kernel, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "launch_ms": 1e3 * t_launch, "flops_per_launch": flops,
-            "issue_peak": ALU_PEAK_TFLOPS, "frac_of_issue_peak": achieved / ALU_PEAK_TFLOPS,
-            "issue_peak_note": "add/mul issue rate, one operation per lane per clock at 2.4 GHz; the "
-                               "bit-exact operation order has no FMA"}
+            "issue_peak": issue, "frac_of_issue_peak": achieved / issue,
+            "issue_peak_note": "one floating-point lane-instruction per lane per clock at 2.4 GHz, times "
+                               "this kernel's flops per instruction (an FMA carries two)"}
 
 
 def host_info():
@@ -286,6 +292,7 @@ def run_single(args, wl, tile=0, engine="auto", want_naive=True, want_cpu=True):
     spc = info["steps_per_cycle"]
     tiers = spc * TIERS_PER_STEP[wl["kind"]]
     flops = FLOPS_PER_TIER_UPDATE[wl["kind"]] * p.n * tiers
+    instr = FP_INSTR_PER_TIER_UPDATE[wl["kind"]] * p.n * tiers
     roof = None
     if not args.no_dominant:
         d_lo, d_hi = 1, 21
@@ -299,7 +306,7 @@ def run_single(args, wl, tile=0, engine="auto", want_naive=True, want_cpu=True):
             samples.append((b - a) / (d_hi - d_lo))
         t_diamond = statistics.median(samples)
         roof = roofline("swept diamond phase", flops, t_diamond, wl["dtype"],
-                        _traffic_from_profile(wl, info["tile_width"], engine))
+                        _traffic_from_profile(wl, info["tile_width"], engine), fp_instr=instr)
         # a full run's phases: one up, the diamonds, one down
         roof["diamonds_per_run"] = -(-T * TIERS_PER_STEP[wl["kind"]] // tiers) - 1
 
@@ -367,6 +374,7 @@ def run_batch(args, wl):
     t = _time_runs(lambda: b.run(u), args.steps, torch)
     updates = int(n.sum()) * T * args.steps
     flops = FLOPS_PER_TIER_UPDATE[wl["kind"]] * int(n.sum()) * T * TIERS_PER_STEP[wl["kind"]]
+    instr = FP_INSTR_PER_TIER_UPDATE[wl["kind"]] * int(n.sum()) * T * TIERS_PER_STEP[wl["kind"]]
     cpu = None
     if not args.no_cpu_baseline:
         budget = min(T, args.cpu_steps or (2000 if wl["kind"] == "heat" else 200))
@@ -387,7 +395,8 @@ def run_batch(args, wl):
                    "sizes_off_16_lattice": int(np.sum(n % 16 != 0)), "timesteps_per_run": T,
                    "kind": wl["kind"], "engine": engine, "persistent_grid": b.grid,
                    "edge_slot_bytes": b.workspace_bytes, "parallelism": "single GPU"},
-        "roofline": roofline("batched run (whole graph launch)", flops, t / args.steps, wl["dtype"]),
+        "roofline": roofline("batched run (whole graph launch)", flops, t / args.steps, wl["dtype"],
+                             fp_instr=instr),
         "naive": None, "speedup_vs_naive": None, "cpu_baseline": cpu,
     }
     b.close()
@@ -443,9 +452,10 @@ def run_adjoint(args, wl):
 
     # Dominant kernel: the fused reverse region launch (recompute, lambda walk,
     # dJ/dalpha terms).  Algorithmic flops per launch: every tile's region
-    # holds w h cell-updates, each recomputed (4 flops), walked by lambda (4)
-    # and paired with its Laplacian term ((ul + ur) - 2 u: 3, times lambda and
-    # accumulated: 2).
+    # holds w h cell-updates, each recomputed (4 flops in 3 instructions),
+    # walked by lambda (4 in 3) and paired with its Laplacian term (the
+    # recompute's neighbour sum minus 2 u: 2 in one fused multiply-add; times
+    # lambda and accumulated: 2 in one): 12 flops in 8 instructions.
     roof = None
     if not args.no_dominant:
         h = plan.info["steps_per_cycle"]
@@ -458,8 +468,9 @@ def run_adjoint(args, wl):
         t_launch = _reverse_launch_time(lambda steps: AdjointPlan(B, n, dt, dx, steps), fwd,
                                         lambda pk, gk: pk.adjoint(gk, g_u0, g_a), h, r, torch)
         w = plan.info["tile_width"]
-        flops = B * (n // w) * w * h * (4 + 4 + 5)
-        roof = roofline("fused reverse region launch (recompute + lambda + dJ/dalpha)", flops, t_launch, "f64")
+        flops = B * (n // w) * w * h * (4 + 4 + 4)
+        roof = roofline("fused reverse region launch (recompute + lambda + dJ/dalpha)", flops, t_launch, "f64",
+                        fp_instr=B * (n // w) * w * h * (3 + 3 + 2))
     # the same gradient with two-level checkpointing (about sqrt(K) phases per
     # segment: every segment-th phase's edge state kept, the rest recomputed)
     two = None
@@ -527,10 +538,12 @@ def run_ks_adjoint(args, wl):
 
     # Dominant kernel: the fused reverse region launch.  Algorithmic flops per
     # launch: every tile's region holds w h sub-step updates, each recomputed
-    # (20 flops) and walked back by the adjoint: Jf^T w costs 13 (2 for the
-    # nonlinear weight, 2 for the two neighbour weights, 5 products and 4
-    # sums), plus 1 (dt mu, odd tiers) or 3 ((lambda'' + mu) + dt/2 Jf^T mu,
-    # even tiers): 35 per update on average.
+    # (20 flops in 15 instructions) and walked back by the adjoint: Jf^T w
+    # costs 12 in 8 (1 for the nonlinear weight v/(2 dx), 2 for the two
+    # neighbour weights, 5 products and 4 sums in one multiply and 4 fused
+    # multiply-adds), plus 1 in 1 (dt mu, odd tiers) or 3 in 2 ((lambda'' +
+    # mu) + dt/2 Jf^T mu, even tiers): 34 flops in 24.5 instructions per
+    # update on average.
     roof = None
     if not args.no_dominant:
         h = plan.info["steps_per_cycle"]
@@ -543,8 +556,9 @@ def run_ks_adjoint(args, wl):
         t_launch = _reverse_launch_time(lambda steps: KsAdjointPlan(B, n, dt, dx, steps), fwd,
                                         lambda pk, gk: pk.adjoint(gk, g_u0), h, r, torch)
         w = plan.info["tile_width"]
-        flops = B * (n // w) * w * 2 * h * (20 + 15)
-        roof = roofline("fused reverse region launch (recompute + adjoint walk)", flops, t_launch, "f64")
+        flops = B * (n // w) * w * 2 * h * (20 + 14)
+        roof = roofline("fused reverse region launch (recompute + adjoint walk)", flops, t_launch, "f64",
+                        fp_instr=B * (n // w) * w * h * (2 * 15 + 2 * 8 + 1 + 2))
     cpu = None
     if not args.no_cpu_baseline:
         cs = args.cpu_steps or 100

@@ -13,21 +13,27 @@
  * and does not change the numerical scheme (Sec. 2), so the plain timestepper
  * is the reference the swept result must reproduce.
  *
- * Precision and operation order (IEEE-754, round to nearest even, no
- * contraction into FMA: build with -ffp-contract=off, no -ffast-math):
+ * Precision and operation order (IEEE-754, round to nearest even; build with
+ * -ffp-contract=off and no -ffast-math, so the only fused multiply-adds are
+ * the fma() calls written out, each a*b + c rounded once):
  *
  *   Heat (Sec. 4.1, Eq. HeatDisc; Appendix, final FTCS form):
  *       Fo = (alpha*dt)/(dx*dx), c = 1 - 2*Fo   (computed once, in double)
  *       T_i^{m+1} = Fo*(T_{i+1}^m + T_{i-1}^m) + c*T_i^m
+ *                 = fma(Fo, T_{i+1}^m + T_{i-1}^m, c*T_i^m)
  *
  *   Kuramoto-Sivashinsky (Sec. 4.1, Eq. KSDisc; Appendix, RK2 midpoint):
  *       with a=u_{i+1}, b=u_{i-1}, aa=u_{i+2}, bb=u_{i-2}, o=u_i,
  *       nl = (a*a - b*b) * (1/(4dx))                 (u u_x = (u^2/2)_x)
- *       d2 = ((a + b) - 2*o) * (1/dx^2)              (u_xx)
- *       d4 = ((((aa - 4*a) + 6*o) - 4*b) + bb) * (1/dx^4)   (u_xxxx)
+ *       d2 = fma(-2, o, a + b) * (1/dx^2)            (u_xx)
+ *       d4 = (fma(-4, b, fma(6, o, fma(-4, a, aa))) + bb) * (1/dx^4)   (u_xxxx)
  *       f  = -((nl + d2) + d4)
- *       predictor  u^{m+1/2}_i = u^m_i + (dt/2) * f(u^m)_i       for all i, then
- *       final      u^{m+1}_i   = u^m_i + dt * f(u^{m+1/2})_i
+ *       predictor  u^{m+1/2}_i = fma(dt/2, f(u^m)_i, u^m_i)       for all i, then
+ *       final      u^{m+1}_i   = fma(dt, f(u^{m+1/2})_i, u^m_i)
+ *     The multiples 2o, 4a and 4b are exact, so those three fused steps round
+ *     as (a + b) - 2*o, aa - 4*a and x - 4*b would; 6*o is fused into its
+ *     sum.  The flux difference a*a - b*b is left unfused, so it is exactly
+ *     antisymmetric in a and b.
  *     The inverses 1/(4dx), 1/dx^2 and 1/dx^4 = (1/dx^2)^2 are formed once and
  *     multiplied in, as Sec. 5 (division avoidance) describes.  The printed
  *     "+2u_i" in the u_xx numerator is read as "-2u_i" (the central second
@@ -66,7 +72,7 @@ static void heat_step_f64(const double* u, double* v, int64_t n, double fo, doub
     for (int64_t i = 0; i < n; ++i) {
         double left = u[wrap(i - 1, n)];
         double right = u[wrap(i + 1, n)];
-        v[i] = fo * (right + left) + c * u[i];
+        v[i] = fma(fo, right + left, c * u[i]);
     }
 }
 
@@ -74,7 +80,7 @@ static void heat_step_f32(const float* u, float* v, int64_t n, float fo, float c
     for (int64_t i = 0; i < n; ++i) {
         float left = u[wrap(i - 1, n)];
         float right = u[wrap(i + 1, n)];
-        v[i] = fo * (right + left) + c * u[i];
+        v[i] = fmaf(fo, right + left, c * u[i]);
     }
 }
 
@@ -141,7 +147,7 @@ int oracle_heat_f64_mt(double* u, int64_t n, double alpha, double dt, double dx,
         for (int64_t i = 0; i < n; ++i) {
             double left = cur[wrap(i - 1, n)];
             double right = cur[wrap(i + 1, n)];
-            nxt[i] = fo * (right + left) + c * cur[i];
+            nxt[i] = fma(fo, right + left, c * cur[i]);
         }
         double* t = cur; cur = nxt; nxt = t;
     }
@@ -163,7 +169,7 @@ static void heat_ins_step_f64(const double* u, double* v, int64_t n, double fo, 
     for (int64_t i = 0; i < n; ++i) {
         double left = i == 0 ? u[1] : u[i - 1];
         double right = i == n - 1 ? u[n - 2] : u[i + 1];
-        v[i] = fo * (right + left) + c * u[i];
+        v[i] = fma(fo, right + left, c * u[i]);
     }
 }
 
@@ -171,7 +177,7 @@ static void heat_ins_step_f32(const float* u, float* v, int64_t n, float fo, flo
     for (int64_t i = 0; i < n; ++i) {
         float left = i == 0 ? u[1] : u[i - 1];
         float right = i == n - 1 ? u[n - 2] : u[i + 1];
-        v[i] = fo * (right + left) + c * u[i];
+        v[i] = fmaf(fo, right + left, c * u[i]);
     }
 }
 
@@ -231,8 +237,8 @@ static double ks_rhs_f64(const double* v, int64_t n, int64_t i, const ks_consts*
     double a = v[wrap(i + 1, n)];
     double aa = v[wrap(i + 2, n)];
     double nl = (a * a - b * b) * k->i4dx;
-    double d2 = ((a + b) - 2.0 * o) * k->idx2;
-    double d4 = ((((aa - 4.0 * a) + 6.0 * o) - 4.0 * b) + bb) * k->idx4;
+    double d2 = fma(-2.0, o, a + b) * k->idx2;
+    double d4 = (fma(-4.0, b, fma(6.0, o, fma(-4.0, a, aa))) + bb) * k->idx4;
     return -((nl + d2) + d4);
 }
 
@@ -243,8 +249,8 @@ static float ks_rhs_f32(const float* v, int64_t n, int64_t i, float i4dx, float 
     float a = v[wrap(i + 1, n)];
     float aa = v[wrap(i + 2, n)];
     float nl = (a * a - b * b) * i4dx;
-    float d2 = ((a + b) - 2.0f * o) * idx2;
-    float d4 = ((((aa - 4.0f * a) + 6.0f * o) - 4.0f * b) + bb) * idx4;
+    float d2 = fmaf(-2.0f, o, a + b) * idx2;
+    float d4 = (fmaf(-4.0f, b, fmaf(6.0f, o, fmaf(-4.0f, a, aa))) + bb) * idx4;
     return -((nl + d2) + d4);
 }
 
@@ -254,8 +260,8 @@ int oracle_ks_f64(double* u, int64_t n, double dt, double dx, int64_t steps) {
     double* up = (double*)malloc((size_t)n * sizeof(double));
     if (!up) return ORACLE_ENOMEM;
     for (int64_t m = 0; m < steps; ++m) {
-        for (int64_t i = 0; i < n; ++i) up[i] = u[i] + k.dth * ks_rhs_f64(u, n, i, &k);
-        for (int64_t i = 0; i < n; ++i) u[i] = u[i] + k.dt * ks_rhs_f64(up, n, i, &k);
+        for (int64_t i = 0; i < n; ++i) up[i] = fma(k.dth, ks_rhs_f64(u, n, i, &k), u[i]);
+        for (int64_t i = 0; i < n; ++i) u[i] = fma(k.dt, ks_rhs_f64(up, n, i, &k), u[i]);
     }
     free(up);
     return ORACLE_OK;
@@ -269,8 +275,8 @@ int oracle_ks_f32(float* u, int64_t n, double dt, double dx, int64_t steps) {
     float* up = (float*)malloc((size_t)n * sizeof(float));
     if (!up) return ORACLE_ENOMEM;
     for (int64_t m = 0; m < steps; ++m) {
-        for (int64_t i = 0; i < n; ++i) up[i] = u[i] + fdth * ks_rhs_f32(u, n, i, i4dx, idx2, idx4);
-        for (int64_t i = 0; i < n; ++i) u[i] = u[i] + fdt * ks_rhs_f32(up, n, i, i4dx, idx2, idx4);
+        for (int64_t i = 0; i < n; ++i) up[i] = fmaf(fdth, ks_rhs_f32(u, n, i, i4dx, idx2, idx4), u[i]);
+        for (int64_t i = 0; i < n; ++i) u[i] = fmaf(fdt, ks_rhs_f32(up, n, i, i4dx, idx2, idx4), u[i]);
     }
     free(up);
     return ORACLE_OK;
@@ -287,9 +293,9 @@ int oracle_ks_f64_mt(double* u, int64_t n, double dt, double dx, int64_t steps, 
 #pragma omp parallel num_threads(nt)
         {
 #pragma omp for schedule(static)
-            for (int64_t i = 0; i < n; ++i) up[i] = u[i] + k.dth * ks_rhs_f64(u, n, i, &k);
+            for (int64_t i = 0; i < n; ++i) up[i] = fma(k.dth, ks_rhs_f64(u, n, i, &k), u[i]);
 #pragma omp for schedule(static)
-            for (int64_t i = 0; i < n; ++i) u[i] = u[i] + k.dt * ks_rhs_f64(up, n, i, &k);
+            for (int64_t i = 0; i < n; ++i) u[i] = fma(k.dt, ks_rhs_f64(up, n, i, &k), u[i]);
         }
     }
     free(up);
@@ -390,19 +396,27 @@ int oracle_heat_adjoint_f64(const double* u0, const double* y, int64_t n, double
  *   df_{j+1}/dv_j = -(-2 v_j/(4dx) + 1/dx^2 - 4/dx^4)
  *   df_j/dv_j     = -(-2/dx^2 + 6/dx^4)
  *   df_{j+-2}/dv_j = -1/dx^4
- * and the sum is taken in the order w_{j-1}, w_{j+1}, w_j, w_{j-2}, w_{j+2}.
+ * with 2 v_j/(4dx) formed as v_j * (1/(2dx)), 1/(2dx) = 2 * (1/(4dx)) (the
+ * same rounding as (2 v_j) * (1/(4dx))), and the sum taken in the order
+ * w_{j-1}, w_{j+1}, w_j, w_{j-2}, w_{j+2}: the first product rounded, each
+ * later one fused into the running sum.  The update of lambda is
+ * fma(dt/2, Jf(u)^T mu, lambda' + mu).
  * Forward states are recomputed from checkpoints every `ckpt` steps.
  */
 static void ks_jt_f64(const double* v, const double* w, double* out, int64_t n, const ks_consts* k) {
     double c1 = k->idx2 - 4.0 * k->idx4;
     double c0 = -(6.0 * k->idx4 - 2.0 * k->idx2);
     double c2 = -k->idx4;
+    double i2dx = 2.0 * k->i4dx;
     for (int64_t j = 0; j < n; ++j) {
-        double s = 2.0 * v[j] * k->i4dx;
+        double s = v[j] * i2dx;
         double dm = -(s + c1);  /* df_{j-1}/dv_j */
         double dp = -(c1 - s);  /* df_{j+1}/dv_j */
-        out[j] = (((dm * w[wrap(j - 1, n)] + dp * w[wrap(j + 1, n)]) + c0 * w[j]) + c2 * w[wrap(j - 2, n)]) +
-                 c2 * w[wrap(j + 2, n)];
+        double acc = dm * w[wrap(j - 1, n)];
+        acc = fma(dp, w[wrap(j + 1, n)], acc);
+        acc = fma(c0, w[j], acc);
+        acc = fma(c2, w[wrap(j - 2, n)], acc);
+        out[j] = fma(c2, w[wrap(j + 2, n)], acc);
     }
 }
 
@@ -430,8 +444,8 @@ int oracle_ks_adjoint_f64(const double* u0, const double* y, int64_t n, double d
     memcpy(seg, u0, (size_t)n * sizeof(double));
     for (int64_t m = 0; m < steps; ++m) {
         if (m % K == 0) memcpy(cks + (m / K) * n, seg, (size_t)n * sizeof(double));
-        for (int64_t i = 0; i < n; ++i) q[i] = seg[i] + k.dth * ks_rhs_f64(seg, n, i, &k);
-        for (int64_t i = 0; i < n; ++i) t1[i] = seg[i] + k.dt * ks_rhs_f64(q, n, i, &k);
+        for (int64_t i = 0; i < n; ++i) q[i] = fma(k.dth, ks_rhs_f64(seg, n, i, &k), seg[i]);
+        for (int64_t i = 0; i < n; ++i) t1[i] = fma(k.dt, ks_rhs_f64(q, n, i, &k), seg[i]);
         memcpy(seg, t1, (size_t)n * sizeof(double));
     }
     acc_t ja = {0.0, 0.0};
@@ -447,16 +461,16 @@ int oracle_ks_adjoint_f64(const double* u0, const double* y, int64_t n, double d
         memcpy(seg, cks + (s0 / K) * n, (size_t)n * sizeof(double));
         for (int64_t m = s0; m < s1 - 1; ++m) {
             double* u = seg + (m - s0) * n;
-            for (int64_t i = 0; i < n; ++i) q[i] = u[i] + k.dth * ks_rhs_f64(u, n, i, &k);
-            for (int64_t i = 0; i < n; ++i) u[n + i] = u[i] + k.dt * ks_rhs_f64(q, n, i, &k);
+            for (int64_t i = 0; i < n; ++i) q[i] = fma(k.dth, ks_rhs_f64(u, n, i, &k), u[i]);
+            for (int64_t i = 0; i < n; ++i) u[n + i] = fma(k.dt, ks_rhs_f64(q, n, i, &k), u[i]);
         }
         for (int64_t m = s1 - 1; m >= s0; --m) {
             double* u = seg + (m - s0) * n;
-            for (int64_t i = 0; i < n; ++i) q[i] = u[i] + k.dth * ks_rhs_f64(u, n, i, &k);
+            for (int64_t i = 0; i < n; ++i) q[i] = fma(k.dth, ks_rhs_f64(u, n, i, &k), u[i]);
             ks_jt_f64(q, lam, mu, n, &k);
             for (int64_t i = 0; i < n; ++i) mu[i] = k.dt * mu[i];
             ks_jt_f64(u, mu, t1, n, &k);
-            for (int64_t i = 0; i < n; ++i) lam[i] = (lam[i] + mu[i]) + k.dth * t1[i];
+            for (int64_t i = 0; i < n; ++i) lam[i] = fma(k.dth, t1[i], lam[i] + mu[i]);
         }
     }
     memcpy(g_u0, lam, (size_t)n * sizeof(double));

@@ -1,9 +1,10 @@
 """Build step for the HIP library: compiles csrc/*.hip for gfx950 into
 ``libswept.so`` next to this file (in-tree, so it travels with the source).
 
-Flags: -O3, no FMA contraction (-ffp-contract=off: every kernel must round
-exactly like the plain timestepper), no fast-math, packed-FP32 instructions
-disabled, position-independent shared object.
+Flags: -O3, no FMA contraction by the compiler (-ffp-contract=off: the only
+fused multiply-adds are the ones the stencil code writes out, so every kernel
+rounds exactly like the plain timestepper), no fast-math, packed-FP32
+instructions disabled, position-independent shared object.
 """
 from __future__ import annotations
 

@@ -120,7 +120,8 @@ region_kernel(const double* __restrict__ ustart, const double* __restrict__ ck_i
   // u(x+1,d-1)) - 2 u(x,d-1), formed from the neighbour sum the update uses.
   // Only dJ/dalpha reads it, a sum that matches the reference to rounding
   // rather than bit for bit, so it and the sum's terms use fused
-  // multiply-adds; lambda and dJ/du0 keep the plain update order.
+  // multiply-adds of their own; lambda and dJ/du0 keep the update order of
+  // heat_update.
   double lap[2 * kH];
   double top = 0.0;  // the region's row at tier h
   double tipL = 0.0, tipR = 0.0;  // points -1 and w at tier h-1
@@ -144,7 +145,7 @@ region_kernel(const double* __restrict__ ustart, const double* __restrict__ ck_i
       }
       const double sum = hi + lo;
       lap[t + 1] = __builtin_fma(-2.0, row, sum);
-      row = k.fo * sum + k.c * row;  // heat_update(lo, row, hi)
+      row = fmadd(k.fo, sum, k.c * row);  // heat_update(lo, row, hi)
     }
     top = row;
   }
@@ -155,7 +156,7 @@ region_kernel(const double* __restrict__ ustart, const double* __restrict__ ck_i
       const double lo = dpp_move0<kDppWaveShr1>(row), hi = dpp_move0<kDppWaveShl1>(row);
       const double sum = hi + lo;
       lap[kH + m] = __builtin_fma(-2.0, row, sum);
-      row = k.fo * sum + k.c * row;  // heat_update(lo, row, hi)
+      row = fmadd(k.fo, sum, k.c * row);  // heat_update(lo, row, hi)
     }
   }
   {
@@ -353,12 +354,12 @@ __device__ __forceinline__ void fma_on(uint64_t m, double a, double b, double& a
 // History writes in place: the new value takes the register of the slot's
 // previous value (dead by then), which the register allocator does not find
 // by itself across the chain loop.  Same operations and rounding as
-// fma(-2, row, sum) and a + b.
+// fma(-2, row, sum) and fma(a, b, c).
 __device__ __forceinline__ void lap_into(double& z, double row, double sum) {
   asm("v_fma_f64 %0, -2.0, %1, %2" : "+v"(z) : "v"(row), "v"(sum));
 }
-__device__ __forceinline__ void add_into(double& z, double a, double b) {
-  asm("v_add_f64 %0, %1, %2" : "+v"(z) : "v"(a), "v"(b));
+__device__ __forceinline__ void fma_into(double& z, double a, double b, double c) {
+  asm("v_fma_f64 %0, %1, %2, %3" : "+v"(z) : "v"(a), "v"(b), "v"(c));
 }
 
 // Chain position i (layout L = i mod 2): A_i then B_i, then the hand-off
@@ -496,7 +497,7 @@ __device__ __forceinline__ void chain_position(const double* __restrict__ ck_in,
     constexpr int m = s + 2;
     if constexpr (m >= 1 && m <= kH - 1)  // Lambda tier h+m of tile i-1: [m, w-m)
       fma_on(ma[s + 1][1], ZA[m], lap, acc);
-    row = k.fo * sum + k.c * row;  // heat_update(lo, row, hi)
+    row = fmadd(k.fo, sum, k.c * row);  // heat_update(lo, row, hi)
   });
 
   // ---- B_i: Lambda tier h+d+2 of tile i (layout L) beside V tier d of tile
@@ -527,12 +528,12 @@ __device__ __forceinline__ void chain_position(const double* __restrict__ ck_in,
     }
     constexpr int m = d + 2;
     // heat_update(lo, lam, hi); Lambda tier h+m of tile i is kept for A_{i+1}
-    const double t0 = k.fo * (hi + lo), t1 = k.c * lam;
+    const double sum = hi + lo, t1 = k.c * lam;
     if constexpr (m >= 1 && m <= kH - 1) {
-      add_into(ZB[m], t0, t1);
+      fma_into(ZB[m], k.fo, sum, t1);
       lam = ZB[m];
     } else {
-      lam = t0 + t1;
+      lam = fmadd(k.fo, sum, t1);
     }
     if constexpr (d >= 1) {
       // dJ/dalpha term of V tier d of tile i-1, gap [a-d, a+d)

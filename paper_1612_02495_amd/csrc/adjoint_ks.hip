@@ -11,7 +11,9 @@
 //   (2 v_i / (4 dx)) (w_{i-1} - w_{i+1}) + (w_{i-1} + w_{i+1} - 2 w_i)/dx^2
 //   + (w_{i-2} - 4 w_{i-1} + 6 w_i - 4 w_{i+1} + w_{i+2})/dx^4, negated,
 // evaluated with per-neighbour coefficients in the fixed order w_{i-1},
-// w_{i+1}, w_i, w_{i-2}, w_{i+2}, no contraction.
+// w_{i+1}, w_i, w_{i-2}, w_{i+2}: the first product rounded, each later one
+// fused into the running sum.  The even-tier combination
+// (lambda' + mu) + (dt/2) g is one fused multiply-add on the rounded sum.
 //
 // In tier terms (tier 2m = u after m steps, tier 2m+1 = predictor) the
 // adjoint at tier d needs the adjoint at tier d+1 within two points and, for
@@ -58,7 +60,7 @@ constexpr int kFwdPoints = 4;  // points per lane (and tiles per wave) of the ch
 
 // Coefficients of Jf(v)^T, formed on the host in FP64.
 struct JtCoef {
-  double i4dx;  // 1/(4 dx)
+  double i2dx;  // 1/(2 dx) = 2 (1/(4 dx)), so v i2dx rounds as (2 v) (1/(4 dx))
   double c1;    // idx2 - 4 idx4: the linear part of the w_{i-1}, w_{i+1} weights
   double c0;    // -(6 idx4 - 2 idx2): weight of w_i
   double c2;    // -idx4: weight of w_{i-2}, w_{i+2}
@@ -67,10 +69,10 @@ struct JtCoef {
 // (Jf(v)^T w)_i from v_i and w at i-2 .. i+2.
 __device__ __forceinline__ double jt(double v, double wl2, double wl1, double w, double wr1, double wr2,
                                      const JtCoef& c) {
-  const double s = (2.0 * v) * c.i4dx;
+  const double s = v * c.i2dx;
   const double dm = -(s + c.c1);  // d f_{i-1} / d v_i
   const double dp = -(c.c1 - s);  // d f_{i+1} / d v_i
-  return (((dm * wl1 + dp * wr1) + c.c0 * w) + c.c2 * wl2) + c.c2 * wr2;
+  return fmadd(c.c2, wr2, fmadd(c.c2, wl2, fmadd(c.c0, w, fmadd(dp, wr1, dm * wl1))));
 }
 
 using wave::lanes;
@@ -391,7 +393,7 @@ region_kernel(const double* __restrict__ ustart, const double* __restrict__ ck_i
         Nb nb = nbrs(lam);
         if (HL && d == kH) fix_ends(nb, ll0, ll1, lr0, lr1);
         const double g = jt(hist[d], nb.l2, nb.l1, lam, nb.r1, nb.r2, c);
-        const double nw = (d & 1) ? k.dt * g : (lam2 + lam) + k.dth * g;
+        const double nw = (d & 1) ? k.dt * g : fmadd(k.dth, g, lam2 + lam);
         lam2 = lam;
         lam = nw;
         if (HL && d > kH) {
@@ -451,7 +453,7 @@ rem_pred_kernel(const double* __restrict__ u, double* __restrict__ q, Consts<dou
   if (i >= total) return;
   const double* v = u + (i / n) * n;
   const int64_t x = i % n;
-  q[i] = v[x] + k.dth * rhs_at(v, x, n, k);
+  q[i] = fmadd(k.dth, rhs_at(v, x, n, k), v[x]);  // ks_predictor
 }
 
 // ... then u' = u + dt f(q), out of place.
@@ -462,7 +464,7 @@ rem_final_kernel(const double* __restrict__ u, const double* __restrict__ q, dou
   if (i >= total) return;
   const double* w = q + (i / n) * n;
   const int64_t x = i % n;
-  un[i] = u[i] + k.dt * rhs_at(w, x, n, k);
+  un[i] = fmadd(k.dt, rhs_at(w, x, n, k), u[i]);  // ks_final
 }
 
 // Leading classic steps, reverse: mu = dt Jf(q)^T lambda', with q at the
@@ -476,7 +478,7 @@ rem_mu_kernel(const double* __restrict__ u, const double* __restrict__ lin, doub
   const int64_t x = i % n;
   const double* v = u + row;
   const double* l = lin + row;
-  const double q = v[x] + k.dth * rhs_at(v, x, n, k);
+  const double q = fmadd(k.dth, rhs_at(v, x, n, k), v[x]);
   mu[i] = k.dt * jt(q, l[wrap(x, -2, n)], l[wrap(x, -1, n)], l[x], l[wrap(x, 1, n)], l[wrap(x, 2, n)], c);
 }
 
@@ -490,7 +492,7 @@ rem_lam_kernel(const double* __restrict__ u, const double* __restrict__ lin, con
   const int64_t x = i % n;
   const double* m = mu + row;
   const double g = jt(u[i], m[wrap(x, -2, n)], m[wrap(x, -1, n)], m[x], m[wrap(x, 1, n)], m[wrap(x, 2, n)], c);
-  lout[i] = (lin[i] + mu[i]) + k.dth * g;
+  lout[i] = fmadd(k.dth, g, lin[i] + mu[i]);
 }
 
 }  // namespace ksadj
@@ -568,7 +570,7 @@ int swept_ks_adjoint_create(swept_ks_adjoint* out, int32_t batch, int64_t n, int
   a->k.idx4 = a->k.idx2 * a->k.idx2;
   a->k.dt = dt;
   a->k.dth = 0.5 * dt;
-  a->c.i4dx = a->k.i4dx;
+  a->c.i2dx = 2.0 * a->k.i4dx;
   a->c.c1 = a->k.idx2 - 4.0 * a->k.idx4;
   a->c.c0 = -(6.0 * a->k.idx4 - 2.0 * a->k.idx2);
   a->c.c2 = -a->k.idx4;

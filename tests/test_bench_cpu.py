@@ -1,6 +1,6 @@
 """Host-side checks of bench.py: it measures one GPU and refuses more, its
 roofline fraction is taken against MI355X's published vector peak for the
-dtype (with the add/mul issue rate as a second figure), the traffic figure is
+dtype (with the instruction issue rate as a second figure), the traffic figure is
 read from the committed counter summary only while the kernel sources match
 it, the CPU baseline reports its thread counts and host, and the flop counts
 per update are the stencils' operation counts."""
@@ -23,19 +23,20 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in (r.stdout + r.stderr)
 
 
-def test_alu_peak_is_fp64_lane_ops_without_fma():
-    # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one operation per lane per cycle
-    assert bench.ALU_PEAK_TFLOPS == pytest.approx(256 * 4 * 16 * 2.4e9 / 1e12)
-    assert bench.ALU_PEAK_TFLOPS == pytest.approx(78.6 / 2, rel=1e-3)
+def test_issue_rate_is_fp64_lane_instructions():
+    # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one instruction per lane per cycle
+    assert bench.ALU_ISSUE_TERA == pytest.approx(256 * 4 * 16 * 2.4e9 / 1e12)
+    assert bench.ALU_ISSUE_TERA == pytest.approx(78.6 / 2, rel=1e-3)
 
 
 def test_flops_per_update():
-    # heat: fo*(r+l) + c*o is 4 operations; a KS sub-step is the 5-point
-    # right-hand side (18 operations, the two squares included) plus the
-    # axpy (2), 20 in all
+    # heat: fma(fo, r + l, c*o) is 4 operations in 3 instructions; a KS
+    # sub-step is the 5-point right-hand side (18 operations, the two squares
+    # included, in 14 instructions) plus the fused update (2 in 1)
     assert bench.FLOPS_PER_TIER_UPDATE["heat"] == 4
     assert bench.FLOPS_PER_TIER_UPDATE["heat_insulated"] == 4
     assert bench.FLOPS_PER_TIER_UPDATE["ks"] == 20
+    assert bench.FP_INSTR_PER_TIER_UPDATE == {"heat": 3, "heat_insulated": 3, "ks": 15}
 
 
 def test_traffic_read_only_for_matching_sources(tmp_path, monkeypatch):
@@ -68,6 +69,9 @@ def test_roofline_uses_the_published_peak_and_the_issue_rate():
     assert r["achieved"] == pytest.approx(40.0)
     assert r["peak"] == 78.6 and r["frac"] == pytest.approx(40.0 / 78.6)
     assert r["issue_peak"] == pytest.approx(39.3216) and r["frac_of_issue_peak"] == pytest.approx(40.0 / 39.3216)
+    # four flops in three instructions raise the issue ceiling by 4/3
+    r = bench.roofline("k", flops=4.0e9, t_launch=1e-4, dtype="f64", fp_instr=3.0e9)
+    assert r["issue_peak"] == pytest.approx(39.3216 * 4 / 3) and r["frac"] == pytest.approx(40.0 / 78.6)
     assert r["unit"] == "TFLOP/s" and r["bound"] == "alu" and r["launch_ms"] == pytest.approx(0.1)
     assert bench.roofline("k", 1.0, 1.0, "f32")["peak"] == 157.3
 
