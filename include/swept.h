@@ -400,18 +400,21 @@ int swept_adjoint_create(swept_adjoint* out, int32_t batch, int64_t n, int dtype
 
 /*
  * swept_adjoint_create_segmented -- swept_adjoint_create with two-level
- * checkpointing: the edge state of only every `segment`-th phase (phases 0,
- * segment, 2 segment, ..) is kept by swept_forward_ckpt, and swept_adjoint_run
- * recomputes the edge states of each segment's other phases from its kept
- * state, just before it reverses that segment, into one reused set of
- * segment - 1 buffers.  Checkpoint memory falls from K sets (K = steps / 32)
- * to ceil(K / segment) + segment - 1 sets, at the cost of about one more
- * forward pass in swept_adjoint_run; the gradients are the same bits as with
- * every phase kept (the recomputed states are the same bits).  segment = 1 is
- * swept_adjoint_create; segment = 0 picks ceil(sqrt(K)), about 2 sqrt(K)
- * sets (e.g. 64 grids of 2^18 points over 10^4 steps: 35 sets, 9.7 GB,
- * instead of 312 sets, 86 GB).  Errors as swept_adjoint_create, and EINVAL for
- * segment < 0.
+ * checkpointing: the edge state of only every `segment`-th phase (phases
+ * K mod segment, K mod segment + segment, .., K - segment, with K = steps / 32
+ * phases and `segment` capped at K) is kept by swept_forward_ckpt, and
+ * swept_adjoint_run recomputes the edge states of the other phases, segment by
+ * segment just before it reverses each, from the kept state below them (from
+ * the initial state for the phases below the first kept one) into one reused
+ * set of segment - 1 buffers.  The top segment's states are the forward's
+ * own, left in those buffers.  Checkpoint memory falls from K sets to
+ * floor(K / segment) + segment - 1 sets, at the cost of about one more forward
+ * pass in swept_adjoint_run (K - floor(K / segment) - segment + 1 phases); the
+ * gradients are the same bits as with every phase kept (the recomputed states
+ * are the same bits).  segment = 1 is swept_adjoint_create; segment = 0 picks
+ * ceil(sqrt(K)), about 2 sqrt(K) sets (e.g. 64 grids of 2^18 points over 10^4
+ * steps: 34 sets, 9.4 GB, instead of 312 sets, 86 GB).  Errors as
+ * swept_adjoint_create, and EINVAL for segment < 0.
  */
 int swept_adjoint_create_segmented(swept_adjoint* out, int32_t batch, int64_t n, int dtype, double dt, double dx,
                                    int64_t steps, int segment);

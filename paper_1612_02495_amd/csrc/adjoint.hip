@@ -847,7 +847,8 @@ struct swept_adjoint_s {
   bool poison = false;        // SWEPT_DEBUG_POISON: NaN-fill checkpoints and lambda slots before use
   double* consts = nullptr;   // Consts<double>[batch]
   int Q = 1;                  // phases per checkpoint segment (1: every phase's edge state kept)
-  int nlev = 0;               // kept checkpoint sets: phases 0, Q, 2Q, .. below K
+  int off = 0;                // K mod Q: the first kept phase
+  int nlev = 0;               // kept checkpoint sets: phases off, off + Q, .., K - Q
   double* ckpt = nullptr;     // nlev kept sets, then Q-1 sets of the segment being recomputed;
                               // a set is batch x 2nt x 66 values
   double* lam_slots = nullptr;
@@ -868,23 +869,31 @@ int afail(int code, const std::string& m) { return swept::set_error(code, m); }
 int ahip(hipError_t e, const char* what) { return afail(SWEPT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)); }
 
 // Where the edge state written by phase q (the reverse launch of phase q + 1
-// restarts from it) lives: the kept sets for q = 0, Q, 2Q, .., the segment
-// sets for the phases in between (rewritten segment by segment).
+// restarts from it) lives: the kept sets for q = off, off + Q, .., K - Q, the
+// segment sets for the phases in between and below off (rewritten segment by
+// segment).  The kept grid ends at K - Q so that the top segment, whose
+// states the forward itself leaves in the segment sets, is a full one.
 double* ckpt_set(const swept_adjoint_s* a, int q) {
   const size_t pslots = (size_t)a->batch * 2 * (size_t)a->nt * kSL;
-  if (q % a->Q == 0) return a->ckpt + (size_t)(q / a->Q) * pslots;
-  return a->ckpt + (size_t)(a->nlev + q % a->Q - 1) * pslots;
+  const int d = q - a->off;
+  if (d >= 0 && d % a->Q == 0) return a->ckpt + (size_t)(d / a->Q) * pslots;
+  return a->ckpt + (size_t)(a->nlev + (d % a->Q + a->Q) % a->Q - 1) * pslots;
 }
 
-// Forward phases q0 .. q1 (all with both a V and a Lambda part) from the
-// edge state of phase q0 - 1, each writing its own edge state.
-hipError_t forward_phases(const swept_adjoint_s* a, int q0, int q1, hipStream_t st) {
+// Forward phases q0 .. q1 (all with a Lambda part), each writing its own edge
+// state: from the edge state of phase q0 - 1, or, for q0 = 0, from the state
+// ur after the leading classic steps.
+hipError_t forward_phases(const swept_adjoint_s* a, int q0, int q1, const double* ur, hipStream_t st) {
   constexpr int FP = swept::adj::kFwdPoints;
   const auto* k = reinterpret_cast<const swept::Consts<double>*>(a->consts);
+  const dim3 grid((unsigned)((a->nt + FP - 1) / FP), (unsigned)a->batch);
   for (int q = q0; q <= q1; ++q) {
-    hipLaunchKernelGGL((swept::adj::forward_kernel<FP, true, true>), dim3((unsigned)((a->nt + FP - 1) / FP),
-                       (unsigned)a->batch), dim3(kW), 0, st, nullptr, nullptr, ckpt_set(a, q - 1), ckpt_set(a, q), k,
-                       a->n, a->nt, q);
+    if (q == 0)
+      hipLaunchKernelGGL((swept::adj::forward_kernel<FP, false, true>), grid, dim3(kW), 0, st, ur, nullptr, nullptr,
+                         ckpt_set(a, 0), k, a->n, a->nt, 0);
+    else
+      hipLaunchKernelGGL((swept::adj::forward_kernel<FP, true, true>), grid, dim3(kW), 0, st, nullptr, nullptr,
+                         ckpt_set(a, q - 1), ckpt_set(a, q), k, a->n, a->nt, q);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -945,7 +954,8 @@ int swept_adjoint_create_segmented(swept_adjoint* out, int32_t batch, int64_t n,
     while ((int64_t)Q * Q < a->K) ++Q;
   }
   a->Q = std::max(1, std::min(Q, std::max(1, a->K)));
-  a->nlev = a->K > 0 ? (a->K - 1) / a->Q + 1 : 0;
+  a->off = a->K % a->Q;
+  a->nlev = (a->K - a->off) / a->Q;
   a->poison = swept::debug_poison_requested();
   hipError_t e = hipGetDevice(&a->device);
   if (e != hipSuccess) {
@@ -1040,11 +1050,13 @@ int swept_adjoint_run(swept_adjoint a, const void* g_uT, void* g_u0, double* g_a
   } else {
     const double* ur = a->rem + (size_t)a->r * total;
     for (int p = a->K; p >= 0 && e == hipSuccess; --p) {
-      // entering a segment from its top: recompute the edge states of its
-      // phases from the kept state that starts it
-      if (a->Q > 1 && p >= 2 && (p == a->K || p % a->Q == 0)) {
-        const int q0 = (p - 1) / a->Q * a->Q + 1;
-        if (q0 <= p - 1) e = forward_phases(a, q0, p - 1, st);
+      // entering a segment from its top (phase p kept, p - 1 not): recompute
+      // the edge states of its phases from the kept state below it, or from
+      // ur for the phases below the first kept one.  The top segment's
+      // states are still in the segment sets from the forward.
+      if (a->Q > 1 && p >= 1 && p < a->K && (p - a->off) % a->Q == 0 && p >= a->off) {
+        const int q0 = p == a->off ? 0 : p - a->Q + 1;
+        e = forward_phases(a, q0, p - 1, ur, st);
         if (e != hipSuccess) break;
       }
       const double* ck_in = p > 0 ? ckpt_set(a, p - 1) : nullptr;

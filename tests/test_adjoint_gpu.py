@@ -166,7 +166,10 @@ def test_autograd_plans_are_reused_and_never_shared():
     sw.release_cached_plans()
 
 
-@pytest.mark.parametrize("segment,steps", [(0, 32 * 40 + 7), (3, 32 * 10), (5, 32 * 11 + 31), (2, 64), (7, 40)])
+# K = steps // 32 full phases; the first kept phase is K mod Q: 5, 1, 1, 0, 0
+# (Q = 1), 0 and 5 in turn, the last two with segments of 4 and 6 phases
+@pytest.mark.parametrize("segment,steps", [(0, 32 * 40 + 7), (3, 32 * 10), (5, 32 * 11 + 31), (2, 64), (7, 40),
+                                           (4, 32 * 12 + 5), (6, 32 * 17)])
 def test_two_level_checkpointing_gives_the_same_bits(segment, steps):
     # keeping every segment-th phase's edge state and recomputing the others
     # during the reverse sweep gives the gradients of the plan that keeps all
@@ -203,7 +206,7 @@ def test_two_level_checkpointing_gives_the_same_bits(segment, steps):
 
 def test_two_level_checkpoint_memory_of_the_gradient_workload():
     # 64 grids of 2^18 points over 10^4 steps: 312 phases; segments of 18
-    # keep 18 + 17 sets instead of 312 (plan creation only, no run)
+    # keep 17 + 17 sets instead of 312 (plan creation only, no run)
     from paper_1612_02495_amd.swept import swept_adjoint_create_segmented, swept_adjoint_destroy, swept_adjoint_info
     u0s, alpha, u0t, alpha_t, dt, dx, steps = inputs.heat_adjoint(batch=1)
     n = u0s.shape[1]
@@ -211,5 +214,5 @@ def test_two_level_checkpoint_memory_of_the_gradient_workload():
     info = swept_adjoint_info(h)
     swept_adjoint_destroy(h)
     per_set = 64 * 2 * (n // 64) * 66 * 8
-    assert info["checkpoint_bytes"] == 35 * per_set
+    assert info["checkpoint_bytes"] == 34 * per_set
     assert info["checkpoint_bytes"] <= 10e9
