@@ -173,9 +173,9 @@ CSRC = "paper_1612_02495_amd/csrc/"
 # Per engine: the sources that define its diamond kernel; per (kind, dtype,
 # engine): the committed rocprofv3 counter summary of the N=2^20 w=1024 workload.
 KERNEL_SOURCES = {
-    "wave": [CSRC + "phase_wave.hip", CSRC + "stencil.h", CSRC + "internal.h"],
+    "wave": [CSRC + "phase_wave.hip", CSRC + "wave_tile.h", CSRC + "stencil.h", CSRC + "internal.h"],
     "compact": [CSRC + "phase_compact.hip", CSRC + "compact_tile.h", CSRC + "wave_tile.h", CSRC + "stencil.h",
-                CSRC + "internal.h"],
+                CSRC + "internal.h", CSRC + "poison.h"],
 }
 TRAFFIC_SUMMARY = {
     ("heat", "f64", "wave"): "profiles/phase_wave_heat_f64_n2p20_w1024_pmc.md",

@@ -56,7 +56,7 @@ constexpr int kH = kW / (2 * kS);  // 16 tiers (8 steps) per full triangle
 constexpr int kA = kW / 2;         // inner seam
 constexpr int kSL = kW + 2 * kS;
 constexpr int kThreads = 256;
-constexpr int kFwdPoints = 4;  // points per lane (and tiles per wave) of the checkpointing forward
+constexpr int kFwdPoints = 8;  // points per lane (and tiles per wave) of the checkpointing forward
 
 // Coefficients of Jf(v)^T, formed on the host in FP64.
 struct JtCoef {
