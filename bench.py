@@ -33,13 +33,15 @@ if ROOT not in sys.path:
 
 METRIC = "cell-updates/sec, swept vs naive on 1 GPU (FP64 heat/KS); adjoint grad time"
 
-# Algorithmic cost per cell update of one tier (IEEE adds/subtracts/multiplies
-# in stencil.h, a fused multiply-add counting as two; negation is a free
-# source modifier), and the floating-point instructions that carry it:
-#   heat: fma(Fo, r + l, c*o)                     -> 4 flops in 3 instructions
-#   KS:   rhs 18 in 14 + fma(h, rhs, u) 2 in 1    -> 20 in 15  (two sub-steps per step)
+# Algorithmic cost per cell update of one tier, the operations of the
+# discretisation as written in Sec. 4.1 (heat: Fo (r + l) + (1 - 2 Fo) o;
+# KS: the 5-point right-hand side, 18, and the RK2 stage u + h f, 2), and the
+# floating-point instructions that carry it in stencil.h's order (a fused
+# multiply-add is one instruction; negation is a free source modifier):
+#   heat: fma(Fo, r + l, c*o)                                   -> 4 flops in 3 instructions
+#   KS:   u - h g, h g from S1, S2, the flux and two fmas       -> 20 in 11  (two sub-steps per step)
 FLOPS_PER_TIER_UPDATE = {"heat": 4, "heat_insulated": 4, "ks": 20}
-FP_INSTR_PER_TIER_UPDATE = {"heat": 3, "heat_insulated": 3, "ks": 15}
+FP_INSTR_PER_TIER_UPDATE = {"heat": 3, "heat_insulated": 3, "ks": 11}
 TIERS_PER_STEP = {"heat": 1, "heat_insulated": 1, "ks": 2}
 # MI355X's published dense vector peaks (an FMA counts as two operations).
 PUBLISHED_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
@@ -538,11 +540,11 @@ def run_ks_adjoint(args, wl):
 
     # Dominant kernel: the fused reverse region launch.  Algorithmic flops per
     # launch: every tile's region holds w h sub-step updates, each recomputed
-    # (20 flops in 15 instructions) and walked back by the adjoint: Jf^T w
+    # (20 flops in 11 instructions) and walked back by the adjoint: Jf^T w
     # costs 12 in 8 (1 for the nonlinear weight v/(2 dx), 2 for the two
     # neighbour weights, 5 products and 4 sums in one multiply and 4 fused
     # multiply-adds), plus 1 in 1 (dt mu, odd tiers) or 3 in 2 ((lambda'' +
-    # mu) + dt/2 Jf^T mu, even tiers): 34 flops in 24.5 instructions per
+    # mu) + dt/2 Jf^T mu, even tiers): 34 flops in 20.5 instructions per
     # update on average.
     roof = None
     if not args.no_dominant:
@@ -558,7 +560,7 @@ def run_ks_adjoint(args, wl):
         w = plan.info["tile_width"]
         flops = B * (n // w) * w * 2 * h * (20 + 14)
         roof = roofline("fused reverse region launch (recompute + adjoint walk)", flops, t_launch, "f64",
-                        fp_instr=B * (n // w) * w * h * (2 * 15 + 2 * 8 + 1 + 2))
+                        fp_instr=B * (n // w) * w * h * (2 * 11 + 2 * 8 + 1 + 2))
     cpu = None
     if not args.no_cpu_baseline:
         cs = args.cpu_steps or 100

@@ -36,6 +36,14 @@
  *                    nodes, T_{-1} = T_1 and T_n = T_{n-2}.  The rod is laid
  *                    on the same ring of tiles; only the tiles that hold node
  *                    0 or n-1 (where the ring closes) use the ghost values.
+ * Rounding (the paper states no operation order): IEEE round to nearest even,
+ * constants formed on the host in double (rounded once to float for FP32
+ * plans), divisions replaced by products with host-formed inverses (Sec. 5).
+ * The heat update is fma(Fo, T_{i+1} + T_{i-1}, (1 - 2 Fo) T_i), one rounding
+ * of the product-sum.  The KS right-hand side sums its terms left to right,
+ * with the multiples 2u_i, 4u_{i+-1} and 6u_i of the difference numerators
+ * fused into the sums they join and u_{i+1}^2 - u_{i-1}^2 unfused; each RK2
+ * stage is one fused multiply-add, u + (dt/2) f and u + dt f.
  *
  * Conventions shared by all entry points
  *   - Return value: SWEPT_OK (0) or a negative swept status code.  Nothing

@@ -23,22 +23,26 @@
  *                 = fma(Fo, T_{i+1}^m + T_{i-1}^m, c*T_i^m)
  *
  *   Kuramoto-Sivashinsky (Sec. 4.1, Eq. KSDisc; Appendix, RK2 midpoint):
- *       with a=u_{i+1}, b=u_{i-1}, aa=u_{i+2}, bb=u_{i-2}, o=u_i,
- *       nl = (a*a - b*b) * (1/(4dx))                 (u u_x = (u^2/2)_x)
- *       d2 = fma(-2, o, a + b) * (1/dx^2)            (u_xx)
- *       d4 = (fma(-4, b, fma(6, o, fma(-4, a, aa))) + bb) * (1/dx^4)   (u_xxxx)
- *       f  = -((nl + d2) + d4)
- *       predictor  u^{m+1/2}_i = fma(dt/2, f(u^m)_i, u^m_i)       for all i, then
- *       final      u^{m+1}_i   = fma(dt, f(u^{m+1/2})_i, u^m_i)
- *     The multiples 2o, 4a and 4b are exact, so those three fused steps round
- *     as (a + b) - 2*o, aa - 4*a and x - 4*b would; 6*o is fused into its
- *     sum.  The flux difference a*a - b*b is left unfused, so it is exactly
- *     antisymmetric in a and b.
+ *       with a=u_{i+1}, b=u_{i-1}, aa=u_{i+2}, bb=u_{i-2}, o=u_i, the right-
+ *       hand side is f = -g with
+ *       g = (a - b)(a + b)/(4dx)                     (u u_x = (u^2/2)_x)
+ *         + ((a + b) - 2o)/dx^2                      (u_xx)
+ *         + ((aa + bb) - 4(a + b) + 6o)/dx^4         (u_xxxx)
+ *       and each RK2 stage u + h f is formed as u - h g, the step h folded
+ *       into the coefficients h/(4dx), h/dx^2, h/dx^4 (each the double
+ *       product of h and the inverse):
+ *       S1 = a + b, S2 = aa + bb,
+ *       hg = fma(h/dx^4, fma(6, o, fma(-4, S1, S2)),
+ *                fma(h/dx^2, fma(-2, o, S1), (h/(4dx)) * ((a - b) * S1)))
+ *       predictor  u^{m+1/2}_i = u^m_i - hg(u^m)_i      with h = dt/2, for all i, then
+ *       final      u^{m+1}_i   = u^m_i - hg(u^{m+1/2})_i  with h = dt.
  *     The inverses 1/(4dx), 1/dx^2 and 1/dx^4 = (1/dx^2)^2 are formed once and
  *     multiplied in, as Sec. 5 (division avoidance) describes.  The printed
  *     "+2u_i" in the u_xx numerator is read as "-2u_i" (the central second
  *     difference; with "+" the term is not a derivative and sum(u) would not be
- *     conserved).
+ *     conserved).  Every sum is symmetric in the two sides and the flux term
+ *     antisymmetric, so the step maps -u(-x) exactly to the negated mirror of
+ *     the step of u(x).
  *
  *   Periodic boundaries: neighbour i+k is (i+k) mod n (Sec. 4.1; Appendix).
  *
@@ -218,7 +222,11 @@ int oracle_heat_insulated_f32(float* u, int64_t n, double alpha, double dt, doub
 
 /* ------------------------------------------------------------------ KS -- */
 
-typedef struct { double i4dx, idx2, idx4, dt, dth; } ks_consts;
+typedef struct {
+    double i4dx, idx2, idx4, dt, dth;
+    double pnl, p2, p4; /* predictor (h = dt/2): h/(4dx), h/dx^2, h/dx^4 */
+    double fnl, f2, f4; /* final (h = dt) */
+} ks_consts;
 
 static ks_consts ks_make(double dt, double dx) {
     ks_consts k;
@@ -227,31 +235,40 @@ static ks_consts ks_make(double dt, double dx) {
     k.idx4 = k.idx2 * k.idx2;
     k.dt = dt;
     k.dth = 0.5 * dt;
+    k.pnl = k.dth * k.i4dx;
+    k.p2 = k.dth * k.idx2;
+    k.p4 = k.dth * k.idx4;
+    k.fnl = k.dt * k.i4dx;
+    k.f2 = k.dt * k.idx2;
+    k.f4 = k.dt * k.idx4;
     return k;
 }
 
-static double ks_rhs_f64(const double* v, int64_t n, int64_t i, const ks_consts* k) {
+/* h g at point i of the ring v, with cnl = h/(4dx), c2 = h/dx^2, c4 = h/dx^4 */
+static double ks_hg_f64(const double* v, int64_t n, int64_t i, double cnl, double c2, double c4) {
     double bb = v[wrap(i - 2, n)];
     double b = v[wrap(i - 1, n)];
     double o = v[i];
     double a = v[wrap(i + 1, n)];
     double aa = v[wrap(i + 2, n)];
-    double nl = (a * a - b * b) * k->i4dx;
-    double d2 = fma(-2.0, o, a + b) * k->idx2;
-    double d4 = (fma(-4.0, b, fma(6.0, o, fma(-4.0, a, aa))) + bb) * k->idx4;
-    return -((nl + d2) + d4);
+    double s1 = a + b, s2 = aa + bb;
+    double flux = (a - b) * s1;
+    double d2 = fma(-2.0, o, s1);
+    double d4 = fma(6.0, o, fma(-4.0, s1, s2));
+    return fma(c4, d4, fma(c2, d2, cnl * flux));
 }
 
-static float ks_rhs_f32(const float* v, int64_t n, int64_t i, float i4dx, float idx2, float idx4) {
+static float ks_hg_f32(const float* v, int64_t n, int64_t i, float cnl, float c2, float c4) {
     float bb = v[wrap(i - 2, n)];
     float b = v[wrap(i - 1, n)];
     float o = v[i];
     float a = v[wrap(i + 1, n)];
     float aa = v[wrap(i + 2, n)];
-    float nl = (a * a - b * b) * i4dx;
-    float d2 = fmaf(-2.0f, o, a + b) * idx2;
-    float d4 = (fmaf(-4.0f, b, fmaf(6.0f, o, fmaf(-4.0f, a, aa))) + bb) * idx4;
-    return -((nl + d2) + d4);
+    float s1 = a + b, s2 = aa + bb;
+    float flux = (a - b) * s1;
+    float d2 = fmaf(-2.0f, o, s1);
+    float d4 = fmaf(6.0f, o, fmaf(-4.0f, s1, s2));
+    return fmaf(c4, d4, fmaf(c2, d2, cnl * flux));
 }
 
 int oracle_ks_f64(double* u, int64_t n, double dt, double dx, int64_t steps) {
@@ -260,8 +277,8 @@ int oracle_ks_f64(double* u, int64_t n, double dt, double dx, int64_t steps) {
     double* up = (double*)malloc((size_t)n * sizeof(double));
     if (!up) return ORACLE_ENOMEM;
     for (int64_t m = 0; m < steps; ++m) {
-        for (int64_t i = 0; i < n; ++i) up[i] = fma(k.dth, ks_rhs_f64(u, n, i, &k), u[i]);
-        for (int64_t i = 0; i < n; ++i) u[i] = fma(k.dt, ks_rhs_f64(up, n, i, &k), u[i]);
+        for (int64_t i = 0; i < n; ++i) up[i] = u[i] - ks_hg_f64(u, n, i, k.pnl, k.p2, k.p4);
+        for (int64_t i = 0; i < n; ++i) u[i] = u[i] - ks_hg_f64(up, n, i, k.fnl, k.f2, k.f4);
     }
     free(up);
     return ORACLE_OK;
@@ -270,13 +287,13 @@ int oracle_ks_f64(double* u, int64_t n, double dt, double dx, int64_t steps) {
 int oracle_ks_f32(float* u, int64_t n, double dt, double dx, int64_t steps) {
     if (!u || n < 1 || steps < 0) return ORACLE_EINVAL;
     ks_consts k = ks_make(dt, dx);
-    float i4dx = (float)k.i4dx, idx2 = (float)k.idx2, idx4 = (float)k.idx4;
-    float fdt = (float)k.dt, fdth = (float)k.dth;
+    float pnl = (float)k.pnl, p2 = (float)k.p2, p4 = (float)k.p4;
+    float fnl = (float)k.fnl, f2 = (float)k.f2, f4 = (float)k.f4;
     float* up = (float*)malloc((size_t)n * sizeof(float));
     if (!up) return ORACLE_ENOMEM;
     for (int64_t m = 0; m < steps; ++m) {
-        for (int64_t i = 0; i < n; ++i) up[i] = fmaf(fdth, ks_rhs_f32(u, n, i, i4dx, idx2, idx4), u[i]);
-        for (int64_t i = 0; i < n; ++i) u[i] = fmaf(fdt, ks_rhs_f32(up, n, i, i4dx, idx2, idx4), u[i]);
+        for (int64_t i = 0; i < n; ++i) up[i] = u[i] - ks_hg_f32(u, n, i, pnl, p2, p4);
+        for (int64_t i = 0; i < n; ++i) u[i] = u[i] - ks_hg_f32(up, n, i, fnl, f2, f4);
     }
     free(up);
     return ORACLE_OK;
@@ -293,9 +310,9 @@ int oracle_ks_f64_mt(double* u, int64_t n, double dt, double dx, int64_t steps, 
 #pragma omp parallel num_threads(nt)
         {
 #pragma omp for schedule(static)
-            for (int64_t i = 0; i < n; ++i) up[i] = fma(k.dth, ks_rhs_f64(u, n, i, &k), u[i]);
+            for (int64_t i = 0; i < n; ++i) up[i] = u[i] - ks_hg_f64(u, n, i, k.pnl, k.p2, k.p4);
 #pragma omp for schedule(static)
-            for (int64_t i = 0; i < n; ++i) u[i] = fma(k.dt, ks_rhs_f64(up, n, i, &k), u[i]);
+            for (int64_t i = 0; i < n; ++i) u[i] = u[i] - ks_hg_f64(up, n, i, k.fnl, k.f2, k.f4);
         }
     }
     free(up);
@@ -444,8 +461,8 @@ int oracle_ks_adjoint_f64(const double* u0, const double* y, int64_t n, double d
     memcpy(seg, u0, (size_t)n * sizeof(double));
     for (int64_t m = 0; m < steps; ++m) {
         if (m % K == 0) memcpy(cks + (m / K) * n, seg, (size_t)n * sizeof(double));
-        for (int64_t i = 0; i < n; ++i) q[i] = fma(k.dth, ks_rhs_f64(seg, n, i, &k), seg[i]);
-        for (int64_t i = 0; i < n; ++i) t1[i] = fma(k.dt, ks_rhs_f64(q, n, i, &k), seg[i]);
+        for (int64_t i = 0; i < n; ++i) q[i] = seg[i] - ks_hg_f64(seg, n, i, k.pnl, k.p2, k.p4);
+        for (int64_t i = 0; i < n; ++i) t1[i] = seg[i] - ks_hg_f64(q, n, i, k.fnl, k.f2, k.f4);
         memcpy(seg, t1, (size_t)n * sizeof(double));
     }
     acc_t ja = {0.0, 0.0};
@@ -461,12 +478,12 @@ int oracle_ks_adjoint_f64(const double* u0, const double* y, int64_t n, double d
         memcpy(seg, cks + (s0 / K) * n, (size_t)n * sizeof(double));
         for (int64_t m = s0; m < s1 - 1; ++m) {
             double* u = seg + (m - s0) * n;
-            for (int64_t i = 0; i < n; ++i) q[i] = fma(k.dth, ks_rhs_f64(u, n, i, &k), u[i]);
-            for (int64_t i = 0; i < n; ++i) u[n + i] = fma(k.dt, ks_rhs_f64(q, n, i, &k), u[i]);
+            for (int64_t i = 0; i < n; ++i) q[i] = u[i] - ks_hg_f64(u, n, i, k.pnl, k.p2, k.p4);
+            for (int64_t i = 0; i < n; ++i) u[n + i] = u[i] - ks_hg_f64(q, n, i, k.fnl, k.f2, k.f4);
         }
         for (int64_t m = s1 - 1; m >= s0; --m) {
             double* u = seg + (m - s0) * n;
-            for (int64_t i = 0; i < n; ++i) q[i] = fma(k.dth, ks_rhs_f64(u, n, i, &k), u[i]);
+            for (int64_t i = 0; i < n; ++i) q[i] = u[i] - ks_hg_f64(u, n, i, k.pnl, k.p2, k.p4);
             ks_jt_f64(q, lam, mu, n, &k);
             for (int64_t i = 0; i < n; ++i) mu[i] = k.dt * mu[i];
             ks_jt_f64(u, mu, t1, n, &k);

@@ -442,8 +442,9 @@ __device__ __forceinline__ int64_t wrap(int64_t x, int o, int64_t n) {
   return y;
 }
 
-__device__ __forceinline__ double rhs_at(const double* v, int64_t x, int64_t n, const Consts<double>& k) {
-  return ks_rhs(v[wrap(x, -2, n)], v[wrap(x, -1, n)], v[x], v[wrap(x, 1, n)], v[wrap(x, 2, n)], k);
+// The predictor at x of the row v (period n).
+__device__ __forceinline__ double pred_at(const double* v, int64_t x, int64_t n, const Consts<double>& k) {
+  return ks_predictor(v[wrap(x, -2, n)], v[wrap(x, -1, n)], v[x], v[wrap(x, 1, n)], v[wrap(x, 2, n)], k);
 }
 
 // Leading classic steps, forward: q = u + (dt/2) f(u) ...
@@ -453,7 +454,7 @@ rem_pred_kernel(const double* __restrict__ u, double* __restrict__ q, Consts<dou
   if (i >= total) return;
   const double* v = u + (i / n) * n;
   const int64_t x = i % n;
-  q[i] = fmadd(k.dth, rhs_at(v, x, n, k), v[x]);  // ks_predictor
+  q[i] = pred_at(v, x, n, k);
 }
 
 // ... then u' = u + dt f(q), out of place.
@@ -464,7 +465,7 @@ rem_final_kernel(const double* __restrict__ u, const double* __restrict__ q, dou
   if (i >= total) return;
   const double* w = q + (i / n) * n;
   const int64_t x = i % n;
-  un[i] = fmadd(k.dt, rhs_at(w, x, n, k), u[i]);  // ks_final
+  un[i] = ks_final(u[i], w[wrap(x, -2, n)], w[wrap(x, -1, n)], w[x], w[wrap(x, 1, n)], w[wrap(x, 2, n)], k);
 }
 
 // Leading classic steps, reverse: mu = dt Jf(q)^T lambda', with q at the
@@ -478,7 +479,7 @@ rem_mu_kernel(const double* __restrict__ u, const double* __restrict__ lin, doub
   const int64_t x = i % n;
   const double* v = u + row;
   const double* l = lin + row;
-  const double q = fmadd(k.dth, rhs_at(v, x, n, k), v[x]);
+  const double q = pred_at(v, x, n, k);
   mu[i] = k.dt * jt(q, l[wrap(x, -2, n)], l[wrap(x, -1, n)], l[x], l[wrap(x, 1, n)], l[wrap(x, 2, n)], c);
 }
 
@@ -565,11 +566,7 @@ int swept_ks_adjoint_create(swept_ks_adjoint* out, int32_t batch, int64_t n, int
   a->K = (int)(steps / spp);
   a->poison = swept::debug_poison_requested();
   // same formulas as swept_plan_create for SWEPT_KS_RK2 (Sec. 4.1, Sec. 5)
-  a->k.i4dx = 1.0 / (4.0 * dx);
-  a->k.idx2 = 1.0 / (dx * dx);
-  a->k.idx4 = a->k.idx2 * a->k.idx2;
-  a->k.dt = dt;
-  a->k.dth = 0.5 * dt;
+  a->k = swept::make_consts<double>(dt, dx, 0.0);
   a->c.i2dx = 2.0 * a->k.i4dx;
   a->c.c1 = a->k.idx2 - 4.0 * a->k.idx4;
   a->c.c0 = -(6.0 * a->k.idx4 - 2.0 * a->k.idx2);

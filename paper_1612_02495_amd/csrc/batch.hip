@@ -567,18 +567,7 @@ void drop_graph(swept_batch_s* b) {
 
 template <typename T>
 Consts<T> consts_for(double dt, double dx, double alpha) {
-  // same host formulas as swept_plan_create (Sec. 4.1, Sec. 5)
-  const double fo = (alpha * dt) / (dx * dx);
-  const double idx2 = 1.0 / (dx * dx);
-  Consts<T> k;
-  k.fo = (T)fo;
-  k.c = (T)(1.0 - 2.0 * fo);
-  k.i4dx = (T)(1.0 / (4.0 * dx));
-  k.idx2 = (T)idx2;
-  k.idx4 = (T)(idx2 * idx2);
-  k.dt = (T)dt;
-  k.dth = (T)(0.5 * dt);
-  return k;
+  return swept::make_consts<T>(dt, dx, alpha);  // the host formulas of swept_plan_create (Sec. 4.1, Sec. 5)
 }
 
 // Largest grid an engine runs whole in the resident kernels (0: none): with

@@ -288,21 +288,8 @@ int plan_setup(swept_plan_s* p, int64_t n, int kind, int dtype, double dt, doubl
   p->general = general;
   p->nt = general ? swept::general_tiles(stencil_of(kind), n, w) : n / w;
   // Discretisation constants in double, rounded once for float (Sec. 4.1, Sec. 5).
-  const double fo = (alpha * dt) / (dx * dx);
-  p->kd.fo = fo;
-  p->kd.c = 1.0 - 2.0 * fo;
-  p->kd.i4dx = 1.0 / (4.0 * dx);
-  p->kd.idx2 = 1.0 / (dx * dx);
-  p->kd.idx4 = p->kd.idx2 * p->kd.idx2;
-  p->kd.dt = dt;
-  p->kd.dth = 0.5 * dt;
-  p->kf.fo = (float)p->kd.fo;
-  p->kf.c = (float)p->kd.c;
-  p->kf.i4dx = (float)p->kd.i4dx;
-  p->kf.idx2 = (float)p->kd.idx2;
-  p->kf.idx4 = (float)p->kd.idx4;
-  p->kf.dt = (float)p->kd.dt;
-  p->kf.dth = (float)p->kd.dth;
+  p->kd = swept::make_consts<double>(dt, dx, alpha);
+  p->kf = swept::make_consts<float>(dt, dx, alpha);
 
   p->slots_bytes = (size_t)(2 * p->nt) * (size_t)swept::slot_values(w, p->s) * elem_size(dtype);
   if (max_slot_bytes && p->slots_bytes > max_slot_bytes)

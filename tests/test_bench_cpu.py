@@ -30,13 +30,16 @@ def test_issue_rate_is_fp64_lane_instructions():
 
 
 def test_flops_per_update():
-    # heat: fma(fo, r + l, c*o) is 4 operations in 3 instructions; a KS
-    # sub-step is the 5-point right-hand side (18 operations, the two squares
-    # included, in 14 instructions) plus the fused update (2 in 1)
+    # heat: Fo (r + l) + c o is 4 operations, carried by fma(Fo, r + l, c*o)
+    # in 3 instructions; a KS sub-step is the 5-point right-hand side (18
+    # operations, the two squares included) plus the stage update (2), carried
+    # in 11 instructions (two pair sums, the flux difference and product, three
+    # multiply-adds of the numerators, one product and two multiply-adds with
+    # the step-scaled coefficients, the final subtraction)
     assert bench.FLOPS_PER_TIER_UPDATE["heat"] == 4
     assert bench.FLOPS_PER_TIER_UPDATE["heat_insulated"] == 4
     assert bench.FLOPS_PER_TIER_UPDATE["ks"] == 20
-    assert bench.FP_INSTR_PER_TIER_UPDATE == {"heat": 3, "heat_insulated": 3, "ks": 15}
+    assert bench.FP_INSTR_PER_TIER_UPDATE == {"heat": 3, "heat_insulated": 3, "ks": 11}
 
 
 def test_traffic_read_only_for_matching_sources(tmp_path, monkeypatch):
