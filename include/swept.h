@@ -500,7 +500,10 @@ int swept_ks_forward_ckpt(swept_ks_adjoint a, const void* u0, void* uT, void* st
  * g_uT = dJ/du_T (device, batch x n), writes g_u0 = dJ/du_0 (device,
  * batch x n; may not alias g_uT).  For J = 1/2 ||u_T - y||^2, g_uT = u_T - y.
  * Each step is reversed as mu = dt Jf(q)^T lambda',
- * lambda = (lambda' + mu) + (dt/2) Jf(u)^T mu, with q and u recomputed
+ * lambda = (lambda' + mu) + (dt/2) Jf(u)^T mu (the last product-sum one fused
+ * multiply-add; Jf(v)^T w gathered at i from v_i and w_{i-1}, w_{i+1}, w_i,
+ * w_{i-2}, w_{i+2} in that order, each term after the first fused into the
+ * running sum), with q and u recomputed
  * phase by phase from the checkpoints; every swept phase, last to first, is
  * one launch that recomputes its tiles in registers and walks the adjoint
  * back through them.  Deterministic (no atomics, a fixed operation order).
