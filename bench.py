@@ -10,9 +10,9 @@ workloads (4096 grids each) and the heat and KS gradient times.
 
 Every record carries the roofline of its dominant kernel (achieved FLOP/s
 against MI355X's published vector peak for its dtype, and against the
-add/mul issue rate the bit-exact operation order can reach) and the CPU
-oracle's throughput on a bounded sample, single-threaded and on all host
-cores.
+vector issue rate times the kernel's flops per floating-point instruction,
+what its operation order can reach) and the CPU oracle's throughput on a
+bounded sample, single-threaded and on all host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
                     [--workload heat|heat_f32|heat_rod|ks|batch|batch_ks|adjoint|ks_adjoint|sweep]
